@@ -1,0 +1,771 @@
+/*
+ * pv_oracle.c -- plain, sequential CPU reference of the primary-vertex
+ * finding path of arXiv:2412.14966 (LHCb).  TEST INFRASTRUCTURE ONLY: used by
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark;
+ * never by the product path.
+ *
+ * The five steps of Sec. 3 are written out in the paper's order and notation:
+ *   Sec. 3.1  projection to the point of closest approach (Eq. 1, Eq. 3)
+ *   Sec. 3.2  histogram of z_poca with a finite-support kernel whose
+ *             cumulative is a cubic approximation of the Gaussian CDF
+ *   Sec. 3.3  proto-clusters, dip search, z-ordered splitting, seeds (Eq. 4-5)
+ *   Sec. 3.4  explicit association through partition points, iterative
+ *             removal of clusters with too few tracks
+ *   Sec. 3.5  Newton-Raphson vertex fit with Tukey weights (Eq. 6-17),
+ *             followed by the final selection (end of Sec. 3.5, Table 2)
+ * Readings of points the paper leaves open are stated where they are used.
+ *
+ * Nothing here is blocked, fused or reordered for speed: one event at a time,
+ * one track at a time, general 3x3 matrix algebra for the fit.
+ */
+#include "pv_oracle.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* binary32 operations: evaluate in binary64, round once to binary32        */
+/* ------------------------------------------------------------------------ */
+static float add32(float a, float b) { return (float)((double)a + (double)b); }
+static float sub32(float a, float b) { return (float)((double)a - (double)b); }
+static float mul32(float a, float b) { return (float)((double)a * (double)b); }
+static float div32(float a, float b) { return (float)((double)a / (double)b); }
+static float sqrt32(float a) { return (float)sqrt((double)a); }
+
+void orc_params_default(orc_params *p)
+{
+    memset(p, 0, sizeof(*p));
+    /* histogram range of the benchmark workloads; the paper's own range is
+       [-550, 300] mm with the same 0.25 mm bins (Sec. 3.2) */
+    p->z_min = -600.0f;
+    p->z_max = 400.0f;
+    p->dz = 0.25f;
+    p->z_gas = -300.0f;              /* Table 2: p-gas region below -300 mm */
+    p->sigma_max_pp = 1.5f;          /* Sec. 3.2, Table 2 */
+    p->sigma_max_gas = 10.0f;
+    p->u0 = 2.13f;                   /* kernel half-width in units of sigma */
+    p->frac_bits = 16;
+    p->proto_thr = 6554;             /* 0.1 track per bin */
+    p->dip_prom = 131072;            /* 2 tracks per bin */
+    p->min_int_pp = 163840;          /* Table 2: 2.5 tracks */
+    p->min_int_gas = 114688;         /* Table 2: 1.75 tracks */
+    p->part_min_pp = 3;              /* Sec. 3.4 */
+    p->part_min_gas = 2;
+    p->pv_min_pp = 4;                /* Table 2 */
+    p->pv_min_gas = 3;
+    p->max_iter = 10;                /* Sec. 3.5 */
+    p->chi2_max = 12.0;              /* Eq. 17 */
+    p->conv_dchi2 = 0.01;            /* Sec. 3.5, x86 criterion */
+    p->conv_dz = 0.001;              /* 1 micrometre */
+    p->max_rho_pp = 0.3;             /* end of Sec. 3.5 */
+    p->max_tracks = 4096;
+    p->max_vertices = 128;
+}
+
+int orc_nbins(const orc_params *p)
+{
+    double span = ((double)p->z_max - (double)p->z_min) / (double)p->dz;
+    long nb = lround(span);
+    if (!(p->dz > 0.0f) || nb < 1 || fabs(span - (double)nb) > 1e-6 * (double)nb)
+        return -1;
+    return (int)nb;
+}
+
+int orc_gas_bin(const orc_params *p)
+{
+    return (int)floor(((double)p->z_gas - (double)p->z_min) / (double)p->dz);
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.1: projection to the point of closest approach                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Eq. 1: z_poca = z_trk + [(tx - txb)(xb - x) + (ty - tyb)(yb - y)]
+ *                         / [(tx - txb)^2 + (ty - tyb)^2]
+ * Eq. 3: sigma_poca = sqrt(Vxx / [(tx - txb)^2 + (ty - tyb)^2])
+ * Eq. 1 is used as printed, with the beamline's transverse position at z = 0.
+ * The central bin is floor((z_poca - z_min) / dz).  A track enters the
+ * histogram if its inputs are finite, Vxx > 0, the slope difference is
+ * nonzero, z_poca lies in [z_min, z_max) and sigma_poca is at most the
+ * region's maximum (Sec. 3.2); the region is that of the central bin.  It may
+ * be associated to a vertex under the same conditions without the sigma cut
+ * (the paper applies that cut to histogram filling only).
+ */
+int orc_project(const float trk[8], const float beam[4], const orc_params *p,
+                float *zpoca, float *sigma, int *bin)
+{
+    const float x = trk[0], y = trk[1], z = trk[2], tx = trk[3], ty = trk[4], vxx = trk[5];
+    const float xb = beam[0], yb = beam[1], txb = beam[2], tyb = beam[3];
+    int k, flags = 0;
+    *zpoca = 0.0f;
+    *sigma = 0.0f;
+    *bin = -1;
+    for (k = 0; k < 8; ++k)
+        if (!isfinite(trk[k]))
+            return ORC_TR_NONFINITE;
+
+    const float dtx = sub32(tx, txb);
+    const float dty = sub32(ty, tyb);
+    const float dx = sub32(xb, x);
+    const float dy = sub32(yb, y);
+    const float num = add32(mul32(dtx, dx), mul32(dty, dy));
+    const float den = add32(mul32(dtx, dtx), mul32(dty, dty));
+    if (!(den > 0.0f) || !(vxx > 0.0f))
+        return 0;
+    const float zp = add32(z, div32(num, den));
+    const float s2 = div32(vxx, den);
+    const float sg = sqrt32(s2);
+    *zpoca = zp;
+    *sigma = sg;
+    if (!(zp >= p->z_min && zp < p->z_max))
+        return 0;
+    const int nb = orc_nbins(p);
+    int b = (int)floorf(div32(sub32(zp, p->z_min), p->dz));
+    if (b > nb - 1)
+        b = nb - 1;
+    if (b < 0)
+        b = 0;
+    *bin = b;
+    flags |= ORC_TR_ASSOC;
+    const float smax = (b < orc_gas_bin(p)) ? p->sigma_max_gas : p->sigma_max_pp;
+    const float sw = mul32(p->u0, sg);
+    if (s2 <= mul32(smax, smax) && sw > 0.0f)
+        flags |= ORC_TR_HIST;
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.2: histogram filling                                              */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper fills each track as the integral of a Gaussian N(z_poca, sigma)
+ * over every bin near the central one, with a cubic polynomial standing in
+ * for the Gaussian cumulative on the GPU.  Reading: the cubic is
+ *   P(s) = 1/2 + s (3/4 - s^2 / 4),  s = clamp((e - z_poca) / (u0 sigma), -1, 1),
+ * the cumulative of a parabolic kernel of half-width u0 sigma (u0 = 2.13
+ * minimises the largest deviation from the Gaussian cumulative).  Bin j gets
+ * P(e_{j+1}) - P(e_j), in integer units of 2^-frac_bits track, so every
+ * histogrammed track adds exactly 2^frac_bits; the first edge of the
+ * histogram counts as P = 0 and the last as P = 1, so mass beyond the range
+ * lands in the end bins.
+ */
+int orc_edge_code(float e, float zp, float sw, int frac_bits)
+{
+    float s = div32(sub32(e, zp), sw);
+    if (s < -1.0f)
+        s = -1.0f;
+    if (s > 1.0f)
+        s = 1.0f;
+    const float P = add32(0.5f, mul32(s, sub32(0.75f, mul32(0.25f, mul32(s, s)))));
+    /* P * 2^frac_bits is exact; round half to even */
+    return (int)nearbyint((double)P * ldexp(1.0, frac_bits));
+}
+
+static float edge_z(const orc_params *p, int j)
+{
+    return add32(p->z_min, mul32((float)j, p->dz));
+}
+
+void orc_hist_event(const float *const trk[8], int n, const float beam[4],
+                    const orc_params *p, int *h, int *c)
+{
+    const int nb = orc_nbins(p);
+    const int full = 1 << p->frac_bits;
+    int i, j, k;
+    memset(h, 0, sizeof(int) * (size_t)nb);
+    memset(c, 0, sizeof(int) * (size_t)nb);
+    for (i = 0; i < n; ++i) {
+        float t[8], zp, sg;
+        int b;
+        for (k = 0; k < 8; ++k)
+            t[k] = trk[k][i];
+        const int fl = orc_project(t, beam, p, &zp, &sg, &b);
+        if (fl & ORC_TR_ASSOC)
+            c[b] += 1;
+        if (!(fl & ORC_TR_HIST))
+            continue;
+        const float sw = mul32(p->u0, sg);
+        /* edges with nonzero, non-full code lie strictly inside (zp - sw, zp + sw);
+           widen by one edge each side so the end codes are 0 and 'full' */
+        int jl = (int)floor(((double)zp - (double)sw - (double)p->z_min) / (double)p->dz) - 1;
+        int jh = (int)ceil(((double)zp + (double)sw - (double)p->z_min) / (double)p->dz) + 1;
+        if (jl < 0)
+            jl = 0;
+        if (jh > nb)
+            jh = nb;
+        int prev = (jl == 0) ? 0 : orc_edge_code(edge_z(p, jl), zp, sw, p->frac_bits);
+        for (j = jl; j < jh; ++j) {
+            const int next = (j + 1 == nb) ? full : orc_edge_code(edge_z(p, j + 1), zp, sw, p->frac_bits);
+            h[j] += next - prev;
+            prev = next;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.3: peak search                                                    */
+/* ------------------------------------------------------------------------ */
+static int first_argmax(const int *h, int a, int b)
+{
+    int i = a, j;
+    for (j = a + 1; j <= b; ++j)
+        if (h[j] > h[i])
+            i = j;
+    return i;
+}
+
+static int64_t range_sum(const int *h, int a, int b)
+{
+    int64_t s = 0;
+    int j;
+    for (j = a; j <= b; ++j)
+        s += h[j];
+    return s;
+}
+
+/* cluster-integral threshold for the region of the candidate's highest bin
+   (Table 2: 2.5 tracks pp, 1.75 tracks p-gas) */
+static int64_t integral_threshold(const int *h, int a, int b, const orc_params *p)
+{
+    return (first_argmax(h, a, b) < orc_gas_bin(p)) ? p->min_int_gas : p->min_int_pp;
+}
+
+/* Eq. 4-5: z_seed = z_i + delta dz with
+   delta = 1/2 (N_{i+1} - N_{i-1}) / (2 N_i - N_{i+1} - N_{i-1}), in [-1/2, 1/2] */
+double orc_seed_z(const int *h, int nb, int i, const orc_params *p)
+{
+    const double Ni = h[i];
+    const double Nm = (i > 0) ? h[i - 1] : 0.0;
+    const double Np = (i + 1 < nb) ? h[i + 1] : 0.0;
+    const double den = 2.0 * Ni - Np - Nm;
+    double delta = (den > 0.0) ? 0.5 * (Np - Nm) / den : 0.0;
+    if (delta > 0.5)
+        delta = 0.5;
+    if (delta < -0.5)
+        delta = -0.5;
+    const double zi = (double)p->z_min + ((double)i + 0.5) * (double)p->dz;
+    return zi + delta * (double)p->dz;
+}
+
+/*
+ * Proto-clusters are maximal runs of bins with content above proto_thr.
+ * Inside each, a walk with hysteresis dip_prom records the significant
+ * minima: a minimum is recorded once the content has fallen by at least
+ * dip_prom below the preceding maximum and risen again by at least dip_prom
+ * above it (so each recorded minimum has a maximum on either side); of a flat
+ * minimum the lowest-z bin is kept.  The minima are then taken in z order
+ * (the paper's GPU variant): the proto-cluster is cut after minimum m if the
+ * part left of the cut (from the previous cut) and everything right of it up
+ * to the proto-cluster's end both reach the cluster-integral threshold of
+ * their region.  The remainder is a cluster if it reaches the threshold.
+ */
+int orc_peak_search(const int *h, const orc_params *p, orc_cluster *out,
+                    int max_out, int *overflow)
+{
+    const int nb = orc_nbins(p);
+    const int T = p->proto_thr, D = p->dip_prom;
+    int n_out = 0, j = 0;
+    int *minima = (int *)malloc(sizeof(int) * (size_t)nb);
+    *overflow = 0;
+    while (j < nb) {
+        if (h[j] <= T) {
+            ++j;
+            continue;
+        }
+        const int s = j;
+        while (j + 1 < nb && h[j + 1] > T)
+            ++j;
+        const int e = j;
+        ++j;
+
+        /* dip search */
+        int n_min = 0, up = 1, M = h[s], m = 0, mj = -1, k;
+        for (k = s + 1; k <= e; ++k) {
+            if (up) {
+                if (h[k] > M) {
+                    M = h[k];
+                } else if (h[k] <= M - D) {
+                    up = 0;
+                    m = h[k];
+                    mj = k;
+                }
+            } else {
+                if (h[k] < m) {
+                    m = h[k];
+                    mj = k;
+                } else if (h[k] >= m + D) {
+                    minima[n_min++] = mj;
+                    up = 1;
+                    M = h[k];
+                }
+            }
+        }
+
+        /* z-ordered splitting */
+        int cs = s, q, lo = 0, hi = 0;
+        for (q = 0; q <= n_min; ++q) {
+            int emit = 0;
+            if (q < n_min) {
+                const int cut = minima[q];
+                if (range_sum(h, cs, cut) >= integral_threshold(h, cs, cut, p) &&
+                    range_sum(h, cut + 1, e) >= integral_threshold(h, cut + 1, e, p)) {
+                    lo = cs;
+                    hi = cut;
+                    emit = 1;
+                    cs = cut + 1;
+                }
+            } else if (range_sum(h, cs, e) >= integral_threshold(h, cs, e, p)) {
+                lo = cs;
+                hi = e;
+                emit = 1;
+            }
+            if (!emit)
+                continue;
+            if (n_out < max_out) {
+                orc_cluster *cl = &out[n_out];
+                memset(cl, 0, sizeof(*cl));
+                cl->lo = lo;
+                cl->hi = hi;
+                cl->peak = first_argmax(h, lo, hi);
+                cl->z_seed = orc_seed_z(h, nb, cl->peak, p);
+                cl->kept = 1;
+                ++n_out;
+            } else {
+                *overflow = 1;
+            }
+        }
+    }
+    free(minima);
+    return n_out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.4: explicit track association                                     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The partition point between consecutive clusters is the bin halfway
+ * between the first one's upper bound and the next one's lower bound
+ * (rounded down); a cluster owns the bins above the previous partition point
+ * up to and including its own, the first from bin 0 and the last to the end.
+ * Its track count is the number of associable tracks whose central bin it
+ * owns.  While some cluster has fewer tracks than its region's minimum (3 pp,
+ * 2 p-gas), the one with the fewest tracks (lowest z on ties) is removed and
+ * the partition is redone; the paper removes one cluster per round.
+ */
+int orc_partition(orc_cluster *cl, int n_cl, const int *c, const orc_params *p)
+{
+    const int nb = orc_nbins(p);
+    const int gas_bin = orc_gas_bin(p);
+    int *live = (int *)malloc(sizeof(int) * (size_t)(n_cl > 0 ? n_cl : 1));
+    int i, k, b;
+    for (i = 0; i < n_cl; ++i) {
+        cl[i].kept = 1;
+        cl[i].n_assoc = 0;
+        cl[i].own_lo = -1;
+        cl[i].own_hi = -1;
+    }
+    for (;;) {
+        int n_live = 0;
+        for (i = 0; i < n_cl; ++i)
+            if (cl[i].kept)
+                live[n_live++] = i;
+        int prev_p = -1;
+        for (k = 0; k < n_live; ++k) {
+            orc_cluster *a = &cl[live[k]];
+            const int pk = (k + 1 < n_live) ? (a->hi + cl[live[k + 1]].lo) / 2 : nb - 1;
+            a->own_lo = prev_p + 1;
+            a->own_hi = pk;
+            a->n_assoc = 0;
+            for (b = a->own_lo; b <= a->own_hi; ++b)
+                a->n_assoc += c[b];
+            prev_p = pk;
+        }
+        int worst = -1;
+        for (k = 0; k < n_live; ++k) {
+            orc_cluster *a = &cl[live[k]];
+            const int need = (a->peak < gas_bin) ? p->part_min_gas : p->part_min_pp;
+            if (a->n_assoc < need && (worst < 0 || a->n_assoc < cl[worst].n_assoc))
+                worst = live[k];
+        }
+        if (worst < 0) {
+            free(live);
+            return n_live;
+        }
+        cl[worst].kept = 0;
+        cl[worst].n_assoc = 0;
+        cl[worst].own_lo = -1;
+        cl[worst].own_hi = -1;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.5: adaptive vertex fit                                            */
+/* ------------------------------------------------------------------------ */
+/* Eq. 17 */
+static double tukey(double chi2, double chi2_max)
+{
+    if (chi2 < chi2_max) {
+        const double t = 1.0 - chi2 / chi2_max;
+        return t * t;
+    }
+    return 0.0;
+}
+
+/* general 3x3 inverse by the adjugate; returns 0 if the determinant is not
+   positive (the matrices here are symmetric positive semi-definite) */
+static int inverse3(const double a[3][3], double inv[3][3])
+{
+    const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+    const double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+    const double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+    const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+    if (!(det > 0.0) || !isfinite(det))
+        return 0;
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / det;
+    inv[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / det;
+    inv[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / det;
+    inv[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / det;
+    inv[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / det;
+    inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
+    return 1;
+}
+
+/* residual of track i at vertex alpha (Eq. 9) and its chi2 (Eq. 7) */
+static double track_chi2(const float *const trk[8], int i, const double W[2][2],
+                         const double alpha[3], double r[2])
+{
+    const double x = trk[0][i], y = trk[1][i], z = trk[2][i], tx = trk[3][i], ty = trk[4][i];
+    r[0] = x + (alpha[2] - z) * tx - alpha[0];
+    r[1] = y + (alpha[2] - z) * ty - alpha[1];
+    double Wr[2];
+    Wr[0] = W[0][0] * r[0] + W[0][1] * r[1];
+    Wr[1] = W[1][0] * r[0] + W[1][1] * r[1];
+    return r[0] * Wr[0] + r[1] * Wr[1];
+}
+
+static double rel_dist(double q, double t)
+{
+    return fabs(q - t) / t;
+}
+
+/*
+ * Newton-Raphson fit of alpha = (x, y, z) (Eq. 10-16).  W_i = V_i^-1 with
+ * V_i from Eq. 2 evaluated once at the seed z; with x and y uncorrelated and
+ * of identical magnitude, V_i = diag(Vx, Vx) with
+ * Vx = Vxx + 2 dz Vxtx + dz^2 Vtxtx, dz = z_seed - z_trk (a track with
+ * Vx <= 0 keeps weight 0).  Each iteration evaluates residuals, chi2_i and
+ * Tukey weights at the current alpha, forms the gradient and Hessian,
+ * steps alpha_1 = alpha_0 - Hess^-1 grad and predicts
+ * dchi2 = 1/2 (alpha_1 - alpha_0) . grad.  It stops when |dchi2| < conv_dchi2
+ * and |dz_vtx| < conv_dz (x86 criterion), or after max_iter iterations
+ * (flagged as not converged, result kept).  C = (Hess / 2)^-1 of the last
+ * iteration (Eq. 14); the reported weights and chi2 = sum w_i chi2_i are
+ * evaluated at the final alpha, and ndof = 2 sum w - 3.
+ */
+int orc_fit(const float *const trk[8], const int *idx, int n,
+            double x_seed, double y_seed, double z_seed, const orc_params *p,
+            orc_vertex *v, double *w_out)
+{
+    double alpha[3] = {x_seed, y_seed, z_seed};
+    double hess_last[3][3];
+    double *Wd = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int k, it, a, b, converged = 0, n_iter = 0, failed = 0;
+    double margin = INFINITY;
+
+    memset(v, 0, sizeof(*v));
+    memset(hess_last, 0, sizeof(hess_last));
+    v->z_seed = z_seed;
+
+    for (k = 0; k < n; ++k) {
+        const int i = idx[k];
+        const double dz = z_seed - (double)trk[2][i];
+        const double Vx = (double)trk[5][i] + 2.0 * dz * (double)trk[6][i] + dz * dz * (double)trk[7][i];
+        Wd[k] = (Vx > 0.0 && isfinite(Vx)) ? 1.0 / Vx : 0.0;   /* 0 marks an unusable track */
+    }
+
+    for (it = 1; it <= p->max_iter; ++it) {
+        double grad[3] = {0, 0, 0}, hess[3][3], sumw = 0.0;
+        memset(hess, 0, sizeof(hess));
+        for (k = 0; k < n; ++k) {
+            if (Wd[k] == 0.0)
+                continue;
+            const int i = idx[k];
+            const double W[2][2] = {{Wd[k], 0.0}, {0.0, Wd[k]}};
+            const double H[2][3] = {{-1.0, 0.0, (double)trk[3][i]}, {0.0, -1.0, (double)trk[4][i]}};
+            double r[2];
+            const double chi2 = track_chi2(trk, i, W, alpha, r);
+            const double w = tukey(chi2, p->chi2_max);
+            sumw += w;
+            /* grad += 2 w H^T W r ; hess += 2 w H^T W H  (Eq. 10-11) */
+            double WH[2][3];
+            for (a = 0; a < 2; ++a)
+                for (b = 0; b < 3; ++b)
+                    WH[a][b] = W[a][0] * H[0][b] + W[a][1] * H[1][b];
+            const double Wr[2] = {W[0][0] * r[0] + W[0][1] * r[1], W[1][0] * r[0] + W[1][1] * r[1]};
+            for (a = 0; a < 3; ++a) {
+                grad[a] += 2.0 * w * (H[0][a] * Wr[0] + H[1][a] * Wr[1]);
+                for (b = 0; b < 3; ++b)
+                    hess[a][b] += 2.0 * w * (H[0][a] * WH[0][b] + H[1][a] * WH[1][b]);
+            }
+        }
+        double hinv[3][3];
+        if (!(sumw > 0.0) || !inverse3(hess, hinv)) {
+            failed = 1;
+            break;
+        }
+        double d[3];
+        for (a = 0; a < 3; ++a)
+            d[a] = -(hinv[a][0] * grad[0] + hinv[a][1] * grad[1] + hinv[a][2] * grad[2]);
+        const double dchi2 = 0.5 * (d[0] * grad[0] + d[1] * grad[1] + d[2] * grad[2]);   /* Eq. 16 */
+        for (a = 0; a < 3; ++a)
+            alpha[a] += d[a];
+        memcpy(hess_last, hess, sizeof(hess));
+        n_iter = it;
+        v->dchi2 = dchi2;
+
+        /* how close this stop/continue decision came to flipping */
+        const double q1 = fabs(dchi2), q2 = fabs(d[2]);
+        const double r1 = rel_dist(q1, p->conv_dchi2), r2 = rel_dist(q2, p->conv_dz);
+        const int below1 = q1 < p->conv_dchi2, below2 = q2 < p->conv_dz;
+        double frag;
+        if (below1 && below2)
+            frag = (r1 < r2) ? r1 : r2;
+        else if (!below1 && !below2)
+            frag = (r1 > r2) ? r1 : r2;
+        else
+            frag = below1 ? r2 : r1;
+        if (frag < margin)
+            margin = frag;
+
+        if (below1 && below2) {
+            converged = 1;
+            break;
+        }
+    }
+
+    if (failed || n_iter == 0) {
+        free(Wd);
+        v->x = alpha[0];
+        v->y = alpha[1];
+        v->z = alpha[2];
+        v->n_iter = n_iter;
+        v->conv_margin = margin;
+        for (k = 0; k < n; ++k)
+            w_out[k] = 0.0;
+        return 1;
+    }
+
+    /* Eq. 14: C = (1/2 Hess)^-1 */
+    double half[3][3], C[3][3];
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b)
+            half[a][b] = 0.5 * hess_last[a][b];
+    if (!inverse3(half, C)) {
+        free(Wd);
+        for (k = 0; k < n; ++k)
+            w_out[k] = 0.0;
+        return 1;
+    }
+
+    double chi2_tot = 0.0, sumw = 0.0;
+    for (k = 0; k < n; ++k) {
+        if (Wd[k] == 0.0) {
+            w_out[k] = 0.0;
+            continue;
+        }
+        const double W[2][2] = {{Wd[k], 0.0}, {0.0, Wd[k]}};
+        double r[2];
+        const double chi2 = track_chi2(trk, idx[k], W, alpha, r);
+        const double w = tukey(chi2, p->chi2_max);
+        w_out[k] = w;
+        chi2_tot += w * chi2;
+        sumw += w;
+    }
+    free(Wd);
+
+    v->x = alpha[0];
+    v->y = alpha[1];
+    v->z = alpha[2];
+    v->cov[0] = C[0][0];
+    v->cov[1] = C[0][1];
+    v->cov[2] = C[1][1];
+    v->cov[3] = C[0][2];
+    v->cov[4] = C[1][2];
+    v->cov[5] = C[2][2];
+    v->chi2 = chi2_tot;
+    v->ndof = 2.0 * sumw - 3.0;
+    v->n_iter = n_iter;
+    v->flags = converged ? 0 : ORC_VX_NOT_CONVERGED;
+    v->conv_margin = margin;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the whole path                                                           */
+/* ------------------------------------------------------------------------ */
+/*
+ * Per event: project, histogram, peak search (clusters beyond max_vertices,
+ * counted in z order, are dropped and flagged), association, one fit per
+ * surviving cluster, then the final selection: a vertex is kept if its fit
+ * succeeded, its cluster owns at least 4 (pp) / 3 (p-gas) tracks (Table 2),
+ * and, in the pp region, it lies within max_rho_pp of the beamline (end of
+ * Sec. 3.5).  Regions are decided by the cluster's highest bin.  Kept
+ * vertices are written in z (cluster) order; their tracks get the vertex
+ * index and final weight, every other track (-1, 0).
+ */
+static void find_event(const float *const trk[8], int a, int n, const float beam[4],
+                       const orc_params *p, int nb, int *n_vtx, int *status, orc_vertex *vtx,
+                       int *trk_vtx, double *trk_w, int *hist, orc_cluster *clusters,
+                       int *n_clusters, float *trk_zpoca, float *trk_sigma, int *trk_bin)
+{
+    const int maxv = p->max_vertices;
+    const int gas_bin = orc_gas_bin(p);
+    const float *ev[8];
+    int i, k, q;
+    for (k = 0; k < 8; ++k)
+        ev[k] = trk[k] + a;
+    *n_vtx = 0;
+    if (n_clusters)
+        *n_clusters = 0;
+    for (i = 0; i < n; ++i) {
+        trk_vtx[a + i] = -1;
+        trk_w[a + i] = 0.0;
+    }
+    if (n > p->max_tracks) {
+        *status |= ORC_EV_TOO_MANY_TRACKS;
+        if (hist)
+            memset(hist, 0, sizeof(int) * (size_t)nb);
+        return;
+    }
+
+    int *bin = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *fl = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (i = 0; i < n; ++i) {
+        float t[8], zp, sg;
+        for (k = 0; k < 8; ++k)
+            t[k] = ev[k][i];
+        fl[i] = orc_project(t, beam, p, &zp, &sg, &bin[i]);
+        if (fl[i] & ORC_TR_NONFINITE)
+            *status |= ORC_EV_NONFINITE_INPUT;
+        if (trk_zpoca)
+            trk_zpoca[a + i] = zp;
+        if (trk_sigma)
+            trk_sigma[a + i] = sg;
+        if (trk_bin)
+            trk_bin[a + i] = bin[i];
+    }
+
+    int *h = (int *)malloc(sizeof(int) * (size_t)nb);
+    int *c = (int *)malloc(sizeof(int) * (size_t)nb);
+    orc_hist_event(ev, n, beam, p, h, c);
+    if (hist)
+        memcpy(hist, h, sizeof(int) * (size_t)nb);
+
+    orc_cluster *cl = (orc_cluster *)calloc((size_t)(maxv > 0 ? maxv : 1), sizeof(orc_cluster));
+    int overflow = 0;
+    const int ncl = orc_peak_search(h, p, cl, maxv, &overflow);
+    if (overflow)
+        *status |= ORC_EV_VERTEX_OVERFLOW;
+    orc_partition(cl, ncl, c, p);
+    if (clusters) {
+        memcpy(clusters, cl, sizeof(orc_cluster) * (size_t)ncl);
+        *n_clusters = ncl;
+    }
+
+    int *idx = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (q = 0; q < ncl; ++q) {
+        if (!cl[q].kept)
+            continue;
+        int m = 0;
+        for (i = 0; i < n; ++i)
+            if ((fl[i] & ORC_TR_ASSOC) && bin[i] >= cl[q].own_lo && bin[i] <= cl[q].own_hi)
+                idx[m++] = i;
+        const double zs = cl[q].z_seed;
+        const double xs = (double)beam[0] + (double)beam[2] * zs;
+        const double ys = (double)beam[1] + (double)beam[3] * zs;
+        orc_vertex v;
+        const int bad = orc_fit(ev, idx, m, xs, ys, zs, p, &v, w);
+        const int gas = cl[q].peak < gas_bin;
+        int keep = !bad && cl[q].n_assoc >= (gas ? p->pv_min_gas : p->pv_min_pp);
+        if (keep && !gas) {
+            const double bx = v.x - ((double)beam[0] + (double)beam[2] * v.z);
+            const double by = v.y - ((double)beam[1] + (double)beam[3] * v.z);
+            keep = sqrt(bx * bx + by * by) <= p->max_rho_pp;
+        }
+        if (!keep)
+            continue;
+        v.n_tracks = cl[q].n_assoc;
+        v.bin_lo = cl[q].lo;
+        v.bin_hi = cl[q].hi;
+        v.peak_bin = cl[q].peak;
+        const int out = (*n_vtx)++;
+        vtx[out] = v;
+        for (k = 0; k < m; ++k) {
+            trk_vtx[a + idx[k]] = out;
+            trk_w[a + idx[k]] = w[k];
+        }
+    }
+    free(idx);
+    free(w);
+    free(cl);
+    free(h);
+    free(c);
+    free(bin);
+    free(fl);
+}
+
+int orc_find(const float *const trk[8], const int *offsets, int n_events,
+             const float beam[4], const orc_params *p,
+             int *n_vtx, int *status, orc_vertex *vtx, int *trk_vtx, double *trk_w,
+             int *hist, orc_cluster *clusters, int *n_clusters,
+             float *trk_zpoca, float *trk_sigma, int *trk_bin, int n_threads)
+{
+    const int nb = orc_nbins(p);
+    int e;
+    if (nb < 0 || n_events < 0 || !offsets || !p || p->max_vertices < 1 || p->frac_bits < 1 ||
+        p->frac_bits > 20)
+        return -1;
+    if (n_threads <= 0)
+        n_threads = orc_max_threads();
+    const int total = offsets[n_events];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads)
+#endif
+    for (e = 0; e < n_events; ++e) {
+        const int a = offsets[e], b = offsets[e + 1];
+        status[e] = 0;
+        n_vtx[e] = 0;
+        if (n_clusters)
+            n_clusters[e] = 0;
+        if (a < 0 || b < a || b > total) {
+            status[e] = ORC_EV_OFFSETS_INVALID;
+            if (hist)
+                memset(hist + (size_t)e * nb, 0, sizeof(int) * (size_t)nb);
+            continue;
+        }
+        find_event(trk, a, b - a, beam, p, nb, &n_vtx[e], &status[e],
+                   vtx + (size_t)e * p->max_vertices, trk_vtx, trk_w,
+                   hist ? hist + (size_t)e * nb : NULL,
+                   clusters ? clusters + (size_t)e * p->max_vertices : NULL,
+                   n_clusters ? &n_clusters[e] : NULL, trk_zpoca, trk_sigma, trk_bin);
+    }
+    return 0;
+}

@@ -1,0 +1,749 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test ties one oracle function to something other than its own formula:
+closed forms, exact dyadic values, linear error propagation, brute-force
+minimisation, numpy least squares, invariants and a naive re-formulation of
+the integer steps.  A dropped term, a wrong sign or a transposed operand in
+the oracle fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_14966_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 65536
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def trk(x=0.0, y=0.0, z=0.0, tx=0.3, ty=0.0, vxx=1e-3, vxtx=0.0, vtxtx=0.0):
+    return np.array([x, y, z, tx, ty, vxx, vxtx, vtxtx], dtype=np.float32)
+
+
+def f32(v):
+    return float(np.float32(v))
+
+
+# --------------------------------------------------------------------------
+# parameters printed in the paper
+# --------------------------------------------------------------------------
+def test_default_parameters_match_paper_constants():
+    g = {r[0]: float(r[1]) for r in _read_golden("paper_constants.txt")}
+    p = oracle.default_params()
+    U_ = 2 ** p["frac_bits"]
+    assert p["dz"] == g["bin_width_mm"]
+    assert p["sigma_max_pp"] == g["sigma_max_pp_mm"]
+    assert p["sigma_max_gas"] == g["sigma_max_gas_mm"]
+    assert p["z_gas"] == g["z_gas_boundary_mm"]
+    assert p["min_int_pp"] == round(g["min_cluster_integral_pp"] * U_)
+    assert p["min_int_gas"] == round(g["min_cluster_integral_gas"] * U_)
+    assert p["pv_min_pp"] == g["min_tracks_pv_pp"] and p["pv_min_gas"] == g["min_tracks_pv_gas"]
+    assert p["part_min_pp"] == g["min_tracks_partition_pp"]
+    assert p["part_min_gas"] == g["min_tracks_partition_gas"]
+    assert p["chi2_max"] == g["chi2_max_tukey"]
+    assert p["max_iter"] == g["max_iterations"]
+    assert p["conv_dchi2"] == g["conv_dchi2"] and p["conv_dz"] == g["conv_dz_mm"]
+    assert p["max_rho_pp"] == g["max_rho_pp_mm"]
+    assert oracle.nbins() == 4000 and oracle.gas_bin() == 1200
+
+
+# --------------------------------------------------------------------------
+# Eq. 1 and Eq. 3
+# --------------------------------------------------------------------------
+def _ulp32(v):
+    return float(np.spacing(np.float32(abs(v)) if v != 0 else np.float32(1e-30)))
+
+
+def test_eq1_track_through_point_on_beamline():
+    """A track through Q, with the (untilted) beamline through Q, has z_poca = z_Q."""
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        q = np.array([rng.normal(0, 0.05), rng.normal(0, 0.05), rng.uniform(-500, 350)])
+        tx, ty = rng.normal(0, 0.3, 2)
+        L = rng.normal(0, 3.0)
+        t32 = trk(q[0] + tx * L, q[1] + ty * L, q[2] + L, tx, ty)
+        beam = (q[0], q[1], 0.0, 0.0)
+        fl, zp, sg, b = oracle.project(t32, beam)
+        assert fl & oracle.TR_ASSOC
+        # exact z of closest approach for the binary32-rounded inputs, binary64
+        x, y, z, txr, tyr = (float(v) for v in t32[:5])
+        xb, yb = (f32(beam[0]), f32(beam[1]))
+        dt2 = txr * txr + tyr * tyr
+        exact = z - (txr * (x - xb) + tyr * (y - yb)) / dt2
+        bound = 8 * max(_ulp32(z), _ulp32(exact), _ulp32(exact - z))
+        assert abs(zp - exact) <= bound
+
+
+def test_eq1_is_argmin_of_transverse_distance():
+    """Eq. 1 as printed is the z minimising the transverse distance between the
+    track and the line of beam slope through (xb, yb) at z_trk; brute force by
+    fitting the (exactly quadratic) squared distance sampled at five points."""
+    rng = np.random.default_rng(2)
+    for _ in range(500):
+        t32 = trk(rng.normal(0, 1), rng.normal(0, 1), rng.uniform(-200, 200), rng.normal(0, 0.3),
+                  rng.normal(0, 0.3))
+        beam = np.array([rng.normal(0, 1), rng.normal(0, 1), rng.normal(0, 1e-3), rng.normal(0, 1e-3)],
+                        dtype=np.float32)
+        _, zp, _, _ = oracle.project(t32, beam)
+        x, y, z, tx, ty = (float(v) for v in t32[:5])
+        xb, yb, txb, tyb = (float(v) for v in beam)
+        zs = z + np.linspace(-50, 50, 5)
+        d2 = ((x + tx * (zs - z)) - (xb + txb * (zs - z))) ** 2 + ((y + ty * (zs - z)) - (yb + tyb * (zs - z))) ** 2
+        a2, a1, _ = np.polyfit(zs - z, d2, 2)
+        zmin = z - a1 / (2 * a2)
+        assert abs(zp - zmin) <= 1e-4 * max(1.0, abs(zmin - z)) + 8 * _ulp32(zmin)
+
+
+def test_eq3_is_linear_error_propagation_of_eq1():
+    """sigma_poca^2 = Vxx (dz/dx)^2 + Vyy (dz/dy)^2 with Vyy = Vxx, uncorrelated
+    (Sec. 3.1); derivatives by central differences of a binary64 POCA."""
+    rng = np.random.default_rng(3)
+    for _ in range(500):
+        vals = [rng.normal(0, 0.1), rng.normal(0, 0.1), rng.uniform(-100, 100), rng.normal(0, 0.3),
+                rng.normal(0, 0.3), rng.uniform(1e-4, 2.5e-3)]
+        t32 = trk(*vals)
+        beam = (0.01, -0.02, 0.0, 0.0)
+        fl, zp, sg, _ = oracle.project(t32, beam)
+        x, y, z, tx, ty, vxx = (float(v) for v in t32[:6])
+
+        def zpoca(xx, yy):
+            return z - (tx * (xx - f32(beam[0])) + ty * (yy - f32(beam[1]))) / (tx * tx + ty * ty)
+
+        h = 1e-4
+        dzdx = (zpoca(x + h, y) - zpoca(x - h, y)) / (2 * h)
+        dzdy = (zpoca(x, y + h) - zpoca(x, y - h)) / (2 * h)
+        ref = math.sqrt(vxx * (dzdx ** 2 + dzdy ** 2))
+        assert sg == pytest.approx(ref, rel=1e-5)
+
+
+def test_sigma_inversely_proportional_to_slope():
+    """sigma_poca ~ 1/|t| (Sec. 3.1): doubling both slopes halves it exactly
+    (power-of-two scalings are exact in binary32)."""
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        tx, ty = rng.normal(0, 0.2, 2)
+        v = rng.uniform(1e-4, 2.5e-3)
+        _, _, s1, _ = oracle.project(trk(0.01, 0.02, 5.0, tx, ty, v))
+        _, _, s2, _ = oracle.project(trk(0.01, 0.02, 5.0, 2 * tx, 2 * ty, v))
+        assert s2 == s1 / 2
+
+
+def test_eligibility_rules():
+    p = oracle.default_params()
+    # parallel to the beam: no closest approach
+    assert oracle.project(trk(tx=0.0, ty=0.0))[0] == 0
+    # non-finite input
+    assert oracle.project(trk(x=np.nan))[0] == oracle.TR_NONFINITE
+    assert oracle.project(trk(vtxtx=np.inf))[0] == oracle.TR_NONFINITE
+    # zero variance
+    assert oracle.project(trk(vxx=0.0))[0] == 0
+    # out of the histogram range
+    assert oracle.project(trk(z=p["z_max"] + 1.0))[0] == 0
+    assert oracle.project(trk(z=p["z_min"] - 1.0))[0] == 0
+    # sigma cut: pp region max 1.5 mm, gas region max 10 mm (Sec. 3.2)
+    fl, _, sg, _ = oracle.project(trk(z=0.0, tx=0.01, vxx=1e-3))          # sigma = 3.16 mm
+    assert sg > 1.5 and fl == oracle.TR_ASSOC
+    fl, _, sg, _ = oracle.project(trk(z=-400.0, tx=0.01, vxx=1e-3))       # same sigma, gas region
+    assert fl == oracle.TR_ASSOC | oracle.TR_HIST
+    fl, _, sg, _ = oracle.project(trk(z=-400.0, tx=0.003, vxx=1e-3))      # sigma = 10.5 mm
+    assert sg > 10 and fl == oracle.TR_ASSOC
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.2 histogram kernel
+# --------------------------------------------------------------------------
+def test_cubic_kernel_golden_codes_and_masses():
+    rows = _read_golden("cubic_kernel.txt")
+    for r in rows:
+        if r[0] == "code":
+            s, code = float(r[1]), int(r[2])
+            # evaluate at e - zp = s * sw with sw = 1 (exact)
+            assert oracle.edge_code(s, 0.0, 1.0) == code
+    # track centred on the edge z = 0 (bin 2400 starts there) with u0 sigma = 2 dz
+    params = {"u0": 1.0}
+    h, c = oracle.hist_event(trk(0.0, 0.0, 0.0, 1.0, 0.0, 0.25).reshape(1, 8), params=params)
+    masses = {int(r[1]): int(r[2]) for r in rows if r[0] == "mass"}
+    nz = {int(j) - 2400: int(h[j]) for j in np.nonzero(h)[0]}
+    assert nz == masses
+    assert c[2400] == 1 and c.sum() == 1
+
+
+def test_cubic_kernel_approximates_gaussian_cdf():
+    """The kernel stands in for the Gaussian bin integral (Sec. 3.2): its
+    cumulative stays within 0.021 of Phi((e - z_poca)/sigma) everywhere, and
+    u0 = 2.13 is close to the minimax choice."""
+    p = oracle.default_params()
+    u0 = p["u0"]
+    grid = np.linspace(-4.0, 4.0, 4001)   # (e - zp)/sigma
+    codes = np.array([oracle.edge_code(float(g), 0.0, u0, 16) for g in grid]) / U
+    phi = 0.5 * (1 + np.array([math.erf(g / math.sqrt(2)) for g in grid]))
+    err = np.max(np.abs(codes - phi))
+    assert err < 0.021
+
+    def sup_err(u):
+        s = np.clip(grid / u, -1, 1)
+        return np.max(np.abs(0.5 + s * (0.75 - 0.25 * s * s) - phi))
+    assert sup_err(u0) <= min(sup_err(u0 - 0.1), sup_err(u0 + 0.1))
+
+
+def test_histogram_mass_is_exact_per_track():
+    """Each histogrammed track adds exactly 2^16 (Sec. 3.2: contributions add
+    up to unity), including tracks whose kernel crosses the histogram ends."""
+    b = synth.generate("pp_mu5_100ev", n_events=30)
+    r = oracle.find(b, debug=True)
+    hist_ok = 0
+    for e in range(b.n_events):
+        a, z = b.offsets[e], b.offsets[e + 1]
+        ev = np.stack([f[a:z] for f in b.fields()], axis=1)
+        n_hist = sum(oracle.project(t)[0] & oracle.TR_HIST != 0 for t in ev)
+        assert r.hist[e].sum() == U * n_hist
+        hist_ok += n_hist
+    assert hist_ok > 1000
+    edge = np.array([trk(0, 0, -599.9, 0.003, 0.0, 1e-4), trk(0, 0, 399.95, 0.01, 0.0, 1e-4),
+                     trk(0, 0, -600.0, 0.5, 0.5, 1e-4)])
+    h, c = oracle.hist_event(edge)
+    assert h.sum() == 3 * U and h[0] > U and h[-1] > U // 2
+
+
+def test_histogram_matches_gaussian_bin_integrals():
+    """Bin masses agree with the Gaussian integrals over the bins (Sec. 3.2)
+    within twice the kernel's cumulative error."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        z0 = rng.uniform(-100, 100)
+        tx = rng.uniform(0.05, 0.5)
+        v = rng.uniform(1e-4, 2.5e-3)
+        t = trk(0.0, 0.0, z0, tx, 0.0, v)
+        fl, zp, sg, _ = oracle.project(t)
+        h, _ = oracle.hist_event(t.reshape(1, 8))
+        j = np.arange(4000)
+        lo = -600 + 0.25 * j
+        cdf = lambda e: 0.5 * (1 + np.vectorize(math.erf)((e - zp) / (sg * math.sqrt(2))))
+        gauss = cdf(lo + 0.25) - cdf(lo)
+        assert np.max(np.abs(h / U - gauss)) < 0.042
+
+
+def test_histogram_independent_of_track_order_and_window():
+    b = synth.generate("pp_mu5_100ev", n_events=3)
+    for e in range(3):
+        a, z = b.offsets[e], b.offsets[e + 1]
+        ev = np.stack([f[a:z] for f in b.fields()], axis=1)
+        h1, c1 = oracle.hist_event(ev)
+        perm = np.random.default_rng(e).permutation(ev.shape[0])
+        h2, c2 = oracle.hist_event(ev[perm])
+        assert np.array_equal(h1, h2) and np.array_equal(c1, c2)
+    # any superset of the support gives the same integers: sum of per-edge codes
+    t = trk(0.0, 0.0, 1.37, 0.2, 0.1, 1e-3)
+    fl, zp, sg, _ = oracle.project(t)
+    sw = f32(np.float32(2.13) * np.float32(sg))
+    codes = [0] + [oracle.edge_code(f32(-600 + 0.25 * j), zp, sw) for j in range(1, 4000)] + [U]
+    full = np.diff(np.array(codes))
+    h, _ = oracle.hist_event(t.reshape(1, 8))
+    assert np.array_equal(full, h)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.3 peak search
+# --------------------------------------------------------------------------
+def _hist_from(values, start=2000):
+    h = np.zeros(4000, dtype=np.int32)
+    h[start:start + len(values)] = values
+    return h
+
+
+def test_seed_delta_limits():
+    """Eq. 5: symmetric neighbours give delta = 0; N_{i+1} = N_i gives 1/2;
+    |delta| <= 1/2 (Sec. 3.3)."""
+    p = oracle.default_params()
+    h = _hist_from([10, 50, 10])
+    zi = -600 + (2001 + 0.5) * 0.25
+    assert oracle.seed_z(h, 2001) == pytest.approx(zi, abs=1e-12)
+    h = _hist_from([10, 50, 50, 10])
+    assert oracle.seed_z(h, 2001) == pytest.approx(zi + 0.5 * 0.25, abs=1e-12)
+    h = _hist_from([10, 50, 30])
+    assert oracle.seed_z(h, 2001) == pytest.approx(zi + 0.5 * 20 / 60 * 0.25, abs=1e-12)
+    rng = np.random.default_rng(6)
+    for _ in range(2000):
+        v = rng.integers(0, 1000, 3)
+        v[1] = max(v) + rng.integers(0, 5)
+        h = _hist_from(v)
+        d = (oracle.seed_z(h, 2001) - zi) / 0.25
+        assert -0.5 <= d <= 0.5
+
+
+def _naive_peaks(h, p, gas_bin):
+    """Test-only re-formulation of the Sec. 3.3 peak search (z-ordered split)."""
+    T, D = p["proto_thr"], p["dip_prom"]
+
+    def thr(a, b):
+        seg = list(h[a:b + 1])
+        i = a + seg.index(max(seg))
+        return p["min_int_gas"] if i < gas_bin else p["min_int_pp"]
+
+    out = []
+    runs, cur = [], None
+    for j, v in enumerate(h):
+        if v > T:
+            cur = [j, j] if cur is None else [cur[0], j]
+        elif cur is not None:
+            runs.append(cur)
+            cur = None
+    if cur is not None:
+        runs.append(cur)
+    for s, e in runs:
+        minima, state, ref, pos = [], "up", h[s], None
+        for j in range(s + 1, e + 1):
+            v = h[j]
+            if state == "up":
+                if v > ref:
+                    ref = v
+                elif ref - v >= D:
+                    state, ref, pos = "down", v, j
+            else:
+                if v < ref:
+                    ref, pos = v, j
+                elif v - ref >= D:
+                    minima.append(pos)
+                    state, ref = "up", v
+        cs = s
+        for m in minima:
+            if sum(h[cs:m + 1]) >= thr(cs, m) and sum(h[m + 1:e + 1]) >= thr(m + 1, e):
+                out.append((cs, m))
+                cs = m + 1
+        if sum(h[cs:e + 1]) >= thr(cs, e):
+            out.append((cs, e))
+    return out
+
+
+def test_peak_search_matches_naive_formulation():
+    p = oracle.default_params()
+    gb = oracle.gas_bin()
+    rng = np.random.default_rng(7)
+    for trial in range(400):
+        h = np.zeros(4000, dtype=np.int32)
+        start = int(rng.choice([40, 1180, 2000, 3940]))
+        n = int(rng.integers(1, 60))
+        scale = int(rng.choice([3000, 60000, 400000]))
+        h[start:start + n] = rng.integers(0, scale, n)
+        got, ov = oracle.peak_search(h)
+        ref = _naive_peaks(h, p, gb)
+        assert [(int(c["lo"]), int(c["hi"])) for c in got] == ref
+        for c in got:
+            seg = h[c["lo"]:c["hi"] + 1]
+            assert c["peak"] == c["lo"] + int(np.argmax(seg))
+        assert not ov
+
+
+def test_peak_search_hand_cases():
+    p = oracle.default_params()
+    U_ = U
+    # one peak: a cluster spanning the bins above threshold
+    one = _hist_from([1000, 8000, 3 * U_, 6 * U_, 3 * U_, 8000, 1000])
+    cl, _ = oracle.peak_search(one)
+    assert [(c["lo"], c["hi"], c["peak"]) for c in cl] == [(2001, 2005, 2003)]
+    # two peaks, dip deeper than dip_prom, both sides above 2.5 tracks: split at the minimum
+    two = _hist_from([8000, 5 * U_, 8 * U_, 5 * U_, 2 * U_, 5 * U_, 8 * U_, 5 * U_, 8000])
+    cl, _ = oracle.peak_search(two)
+    assert [(c["lo"], c["hi"]) for c in cl] == [(2000, 2004), (2005, 2008)]
+    # dip shallower than dip_prom: one cluster
+    shallow = _hist_from([8000, 5 * U_, 8 * U_, 7 * U_, 6 * U_ + 1, 7 * U_, 8 * U_, 5 * U_, 8000])
+    cl, _ = oracle.peak_search(shallow)
+    assert len(cl) == 1
+    # below the proto-cluster threshold: nothing
+    assert len(oracle.peak_search(_hist_from([6554] * 30))[0]) == 0
+    # split refused when the right part's integral is below 2.5 tracks: the
+    # whole proto-cluster stays one cluster
+    lop = _hist_from([8000, 5 * U_, 8 * U_, 5 * U_, 7000, int(2.2 * U_), 7000])
+    cl, _ = oracle.peak_search(lop)
+    assert [(c["lo"], c["hi"]) for c in cl] == [(2000, 2006)]
+    # a lone cluster of 2 tracks: below the pp threshold (2.5) but above the
+    # gas one (1.75) -> found only in the gas region
+    small = [7000, U_, U_ - 14000, 7000]
+    assert len(oracle.peak_search(_hist_from(small, start=2000))[0]) == 0
+    assert len(oracle.peak_search(_hist_from(small, start=500))[0]) == 1
+
+
+def test_resolution_limit():
+    """Peaks closer than two bins cannot be separated (Sec. 3.2); noise-free
+    vertices 0.25 mm apart give one cluster, 10 mm apart two."""
+    def event(zs, n=20):
+        rows = []
+        rng = np.random.default_rng(8)
+        for z0 in zs:
+            for _ in range(n):
+                tx, ty = rng.normal(0, 0.3, 2)
+                rows.append(trk(0.0, 0.0, z0, tx, ty, 1e-4))
+        return np.array(rows)
+    for zs, expect in (([10.0, 10.25], 1), ([10.0, 20.0], 2)):
+        h, c = oracle.hist_event(event(zs))
+        cl, _ = oracle.peak_search(h)
+        assert len(cl) == expect
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.4 association
+# --------------------------------------------------------------------------
+def _naive_partition(clusters, c, p, gas_bin, nb=4000):
+    alive = list(range(len(clusters)))
+
+    def ranges(al):
+        out = {}
+        prev = -1
+        for k, i in enumerate(al):
+            if k + 1 < len(al):
+                pk = (int(clusters[i]["hi"]) + int(clusters[al[k + 1]]["lo"])) // 2
+            else:
+                pk = nb - 1
+            out[i] = (prev + 1, pk)
+            prev = pk
+        return out
+    while True:
+        rg = ranges(alive)
+        counts = {i: int(c[a:b + 1].sum()) for i, (a, b) in rg.items()}
+        bad = [i for i in alive
+               if counts[i] < (p["part_min_gas"] if clusters[i]["peak"] < gas_bin else p["part_min_pp"])]
+        if not bad:
+            return rg, counts
+        worst = min(bad, key=lambda i: (counts[i], i))
+        alive.remove(worst)
+
+
+def test_partition_matches_naive_formulation():
+    p = oracle.default_params()
+    gb = oracle.gas_bin()
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        k = int(rng.integers(1, 12))
+        edges = np.sort(rng.choice(np.arange(0, 3990), size=2 * k, replace=False))
+        cl = np.zeros(k, dtype=oracle._CLUSTER_DTYPE)
+        for i in range(k):
+            cl[i]["lo"], cl[i]["hi"] = edges[2 * i], edges[2 * i + 1]
+            cl[i]["peak"] = (edges[2 * i] + edges[2 * i + 1]) // 2
+        c = np.zeros(4000, dtype=np.int32)
+        for _ in range(int(rng.integers(0, 40))):
+            c[int(rng.integers(0, 4000))] += int(rng.integers(1, 3))
+        got = oracle.partition(cl, c)
+        rg, counts = _naive_partition(cl, c, p, gb)
+        for i in range(k):
+            if i in rg:
+                assert got[i]["kept"] == 1
+                assert (got[i]["own_lo"], got[i]["own_hi"]) == rg[i]
+                assert got[i]["n_assoc"] == counts[i]
+            else:
+                assert got[i]["kept"] == 0
+
+
+def test_partition_point_is_midway_and_split_minimum_closes_left():
+    cl = np.zeros(2, dtype=oracle._CLUSTER_DTYPE)
+    cl[0]["lo"], cl[0]["hi"], cl[0]["peak"] = 2000, 2010, 2005
+    cl[1]["lo"], cl[1]["hi"], cl[1]["peak"] = 2021, 2030, 2025
+    c = np.zeros(4000, np.int32)
+    c[2015] = 5   # exactly midway: floor((2010 + 2021)/2) = 2015 -> left
+    c[2016] = 5
+    c[0] = 1
+    got = oracle.partition(cl, c)
+    assert (got[0]["own_lo"], got[0]["own_hi"], got[0]["n_assoc"]) == (0, 2015, 6)
+    assert (got[1]["own_lo"], got[1]["own_hi"], got[1]["n_assoc"]) == (2016, 3999, 5)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.5 fit
+# --------------------------------------------------------------------------
+def _exact_tracks_through(P, n, rng, dzs=(0.0, 2.0, -1.5)):
+    """Tracks through P with dyadic slopes so every input is exact in binary32."""
+    rows = []
+    for k in range(n):
+        tx = rng.integers(-40, 41) / 128.0
+        ty = rng.integers(-40, 41) / 128.0
+        if tx == 0 and ty == 0:
+            tx = 0.25
+        d = dzs[k % len(dzs)]
+        rows.append([P[0] + tx * d, P[1] + ty * d, P[2] + d, tx, ty, rng.choice([2.0 ** -13, 2.0 ** -11, 2.0 ** -9]), 0, 0])
+    return np.array(rows, dtype=np.float64)
+
+
+def test_fit_noise_free_vertex_is_exact():
+    """Tracks exactly through P fit back to P; all chi2_i are 0 so every
+    Tukey weight is exactly 1 (Eq. 17)."""
+    rng = np.random.default_rng(10)
+    P = (0.125, -0.0625, 10.5)
+    t = _exact_tracks_through(P, 12, rng)
+    assert np.array_equal(t.astype(np.float32).astype(np.float64), t)
+    bad, v, w = oracle.fit(t, (0.0, 0.0, 10.5 + 0.3))
+    assert not bad
+    assert abs(v["x"] - P[0]) < 1e-9 and abs(v["y"] - P[1]) < 1e-9 and abs(v["z"] - P[2]) < 1e-9
+    assert np.all(np.abs(w - 1.0) < 1e-12)
+    assert v["chi2"] < 1e-12 and v["ndof"] == pytest.approx(2 * 12 - 3)
+
+
+def test_fit_unweighted_limit_is_weighted_least_squares():
+    """Without weights one Newton step is the exact minimum (Sec. 3.5): with
+    chi2_max huge the fit equals numpy least squares on whitened rows, stops
+    after the second (null) step, Eq. 14 gives the inverse normal matrix and
+    the predicted dchi2 of a single step equals the actual chi2 change."""
+    rng = np.random.default_rng(11)
+    params = {"chi2_max": 1e30}
+    for trial in range(50):
+        n = int(rng.integers(3, 40))
+        t = np.zeros((n, 8))
+        t[:, 3:5] = rng.normal(0, 0.3, (n, 2))
+        t[:, 2] = rng.uniform(-3, 3, n) + 7.0
+        t[:, 0:2] = rng.normal(0, 0.05, (n, 2))
+        t[:, 5] = rng.uniform(1e-4, 2.5e-3, n)
+        t[:, 6] = rng.normal(0, 1e-6, n)
+        t[:, 7] = rng.uniform(1e-8, 1e-6, n)
+        t = t.astype(np.float32).astype(np.float64)
+        seed = (0.01, -0.02, 7.2)
+        bad, v, w = oracle.fit(t, seed, params)
+        assert not bad
+        # whitened design: residual_x = (x - z tx) + [-1, 0, tx] . alpha, weight 1/Vx (Eq. 2 at the seed)
+        dz = seed[2] - t[:, 2]
+        Vx = t[:, 5] + 2 * dz * t[:, 6] + dz * dz * t[:, 7]
+        sw = 1 / np.sqrt(Vx)
+        A = np.zeros((2 * n, 3))
+        y = np.zeros(2 * n)
+        A[0::2, 0] = -1
+        A[0::2, 2] = t[:, 3]
+        A[1::2, 1] = -1
+        A[1::2, 2] = t[:, 4]
+        y[0::2] = -(t[:, 0] - t[:, 2] * t[:, 3])
+        y[1::2] = -(t[:, 1] - t[:, 2] * t[:, 4])
+        Aw = A * np.repeat(sw, 2)[:, None]
+        yw = y * np.repeat(sw, 2)
+        sol = np.linalg.lstsq(Aw, yw, rcond=None)[0]
+        assert np.allclose([v["x"], v["y"], v["z"]], sol, atol=1e-9, rtol=0)
+        assert v["n_iter"] == 2
+        C = np.linalg.inv(Aw.T @ Aw)
+        cov = np.array([[v["cov"][0], v["cov"][1], v["cov"][3]], [v["cov"][1], v["cov"][2], v["cov"][4]],
+                        [v["cov"][3], v["cov"][4], v["cov"][5]]])
+        assert np.allclose(cov, C, rtol=1e-9, atol=0)
+        # predicted vs actual chi2 change of one step (Eq. 15-16)
+        bad1, v1, _ = oracle.fit(t, seed, dict(params, max_iter=1))
+
+        def chi2(al):
+            return float(np.sum((Aw @ al - yw) ** 2))
+        actual = chi2(np.array([v1["x"], v1["y"], v1["z"]])) - chi2(np.array(seed))
+        assert v1["dchi2"] == pytest.approx(actual, rel=1e-8, abs=1e-9)
+        assert v1["dchi2"] <= 0
+
+
+def test_fit_tukey_weights_golden():
+    """Weights follow Eq. 17 with chi2_max = 12: a weak probe track is placed
+    at a known chi2 from a vertex pinned by many strong exact tracks."""
+    rng = np.random.default_rng(12)
+    P = (0.0, 0.0, 4.0)
+    strong = _exact_tracks_through(P, 60, rng)
+    strong[:, 5] = 1e-8
+    for chi2_s, w_s in _read_golden("tukey.txt"):
+        chi2, w_ref = float(chi2_s), float(w_s)
+        V = 1e-2
+        r = math.sqrt(chi2 * V)          # chi2 = r^2 / V with the residual along x
+        probe = np.array([[P[0] + r, P[1], P[2], 0.25, 0.125, V, 0, 0]])
+        t = np.concatenate([strong, probe]).astype(np.float32).astype(np.float64)
+        chi2_exact = (float(np.float32(P[0] + r)) - P[0]) ** 2 / float(np.float32(V))
+        bad, v, w = oracle.fit(t, (0.0, 0.0, 4.0))
+        assert not bad
+        w_exact = (1 - chi2_exact / 12) ** 2 if chi2_exact < 12 else 0.0
+        assert w[-1] == pytest.approx(w_exact, abs=1e-6)
+        assert w[-1] == pytest.approx(w_ref, abs=1e-5)
+
+
+def test_covariance_scales_with_track_count():
+    """C (Eq. 14) is symmetric positive definite, and N copies of a track set
+    give C / N."""
+    rng = np.random.default_rng(13)
+    P = (0.0, 0.0, -20.0)
+    base = _exact_tracks_through(P, 7, rng)
+    _, v1, _ = oracle.fit(base, P)
+    _, v4, _ = oracle.fit(np.concatenate([base] * 4), P)
+    c1, c4 = np.array(v1["cov"]), np.array(v4["cov"])
+    assert np.allclose(c4, c1 / 4, rtol=1e-12, atol=0)
+    M = np.array([[c1[0], c1[1], c1[3]], [c1[1], c1[2], c1[4]], [c1[3], c1[4], c1[5]]])
+    assert np.all(np.linalg.eigvalsh(M) > 0)
+
+
+def test_fit_rejects_degenerate_inputs():
+    rng = np.random.default_rng(14)
+    P = (0.0, 0.0, 0.0)
+    # all tracks parallel to the beam axis: z is unconstrained -> singular
+    t = _exact_tracks_through(P, 5, rng)
+    t[:, 3:5] = 0.0
+    bad, _, w = oracle.fit(t, P)
+    assert bad and np.all(w == 0)
+    # no track left inside the Tukey window -> no weight
+    t = _exact_tracks_through(P, 5, rng)
+    t[:, 0] += 5.0
+    bad, _, _ = oracle.fit(t, P)
+    assert bad
+
+
+def test_eq2_extrapolated_variance_is_jacobian_propagation():
+    """Eq. 2 (diagonal part) equals J V J^T for the straight-line Jacobian
+    J = [1, dz] of (x, tx) -> x(z): checked through the weights of an
+    unweighted fit (chi2 computed with 1/Vx)."""
+    rng = np.random.default_rng(15)
+    for _ in range(100):
+        n = 6
+        t = np.zeros((n, 8))
+        t[:, 3:5] = rng.normal(0, 0.3, (n, 2))
+        t[:, 2] = rng.uniform(-3, 3, n)
+        sx = rng.uniform(0.01, 0.05, n)
+        st = rng.uniform(2e-4, 2e-3, n)
+        rho = rng.uniform(-0.6, 0.6, n)
+        t[:, 5], t[:, 6], t[:, 7] = sx * sx, rho * sx * st, st * st
+        t[:, 0:2] = rng.normal(0, 0.03, (n, 2))
+        t = t.astype(np.float32).astype(np.float64)
+        seed = (0.0, 0.0, 0.5)
+        bad, v, w = oracle.fit(t, seed, {"chi2_max": 1e30, "max_iter": 1})
+        alpha = np.array([v["x"], v["y"], v["z"]])
+        chi2 = 0.0
+        for k in range(n):
+            dz = seed[2] - t[k, 2]
+            J = np.array([1.0, dz])
+            V = np.array([[t[k, 5], t[k, 6]], [t[k, 6], t[k, 7]]])
+            var = J @ V @ J
+            rx = t[k, 0] + (alpha[2] - t[k, 2]) * t[k, 3] - alpha[0]
+            ry = t[k, 1] + (alpha[2] - t[k, 2]) * t[k, 4] - alpha[1]
+            chi2 += (rx * rx + ry * ry) / var
+        assert v["chi2"] == pytest.approx(chi2, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# whole path
+# --------------------------------------------------------------------------
+def test_whole_path_noise_free_event_finds_vertices():
+    rng = np.random.default_rng(16)
+    Ps = [(0.01, -0.01, -40.0), (0.0, 0.02, 12.0), (-0.02, 0.0, 60.0)]
+    rows = np.concatenate([_exact_tracks_through(P, 25, rng) for P in Ps])
+    rows = rows.astype(np.float32).astype(np.float64)
+    b = synth.from_tracks([rows])
+    r = oracle.find(b)
+    assert r.n_vertices[0] == 3 and r.status[0] == 0
+    v = r.vertices[0, :3]
+    for k, P in enumerate(Ps):
+        assert abs(v[k]["z"] - P[2]) < 1e-6 and abs(v[k]["x"] - P[0]) < 1e-6
+        assert v[k]["n_tracks"] == 25
+    assert np.all(r.track_weight > 0.999)
+
+
+def test_whole_path_invariant_under_track_shuffle():
+    b = synth.generate("pp_mu5_100ev", n_events=20)
+    r1 = oracle.find(b, debug=True)
+    # shuffle tracks inside each event
+    rng = np.random.default_rng(17)
+    perm = np.concatenate([b.offsets[e] + rng.permutation(b.offsets[e + 1] - b.offsets[e])
+                           for e in range(b.n_events)])
+    b2 = synth.TrackBatch(offsets=b.offsets.copy(), **{f: getattr(b, f)[perm] for f in synth.TRACK_FIELDS})
+    r2 = oracle.find(b2, debug=True)
+    assert np.array_equal(r1.hist, r2.hist)
+    assert np.array_equal(r1.n_vertices, r2.n_vertices)
+    assert np.array_equal(r1.track_vertex[perm], r2.track_vertex)
+    for e in range(b.n_events):
+        n = r1.n_vertices[e]
+        for f in ("x", "y", "z"):
+            assert np.allclose(r1.vertices[e, :n][f], r2.vertices[e, :n][f], atol=1e-9)
+    assert np.allclose(r1.track_weight[perm], r2.track_weight, atol=1e-9)
+
+
+def test_whole_path_recovers_generated_vertices():
+    """Sanity on the synthetic workload: most generated pp vertices with at
+    least 10 tracks are found within 0.5 mm (the paper reports ~96 % above 10
+    tracks on LHCb simulation; this is a self-consistency check only)."""
+    b = synth.generate("pp_mu5_100ev")
+    r = oracle.find(b)
+    found = total = 0
+    for e in range(b.n_events):
+        zs = r.vertices[e, :r.n_vertices[e]]["z"]
+        for pv, nt in zip(b.truth_pvs[e], b.truth_ntracks[e]):
+            if nt >= 10:
+                total += 1
+                found += bool(len(zs) and np.min(np.abs(zs - pv[2])) < 0.5)
+    assert total > 200 and found / total > 0.9
+
+
+def test_batch_composition_and_thread_count_do_not_change_results():
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    full = oracle.find(b, n_threads=4)
+    one = oracle.find(b, n_threads=1)
+    assert np.array_equal(full.track_vertex, one.track_vertex)
+    assert np.array_equal(full.track_weight, one.track_weight)
+    e = 7
+    alone = oracle.find(b.event(e))
+    n = full.n_vertices[e]
+    assert alone.n_vertices[0] == n
+    assert np.array_equal(alone.vertices[0, :n], full.vertices[e, :n])
+
+
+def test_status_bits():
+    b = synth.generate("pp_mu5_100ev", n_events=3)
+    r = oracle.find(b, {"max_tracks": 10})
+    assert np.all(r.status & oracle.EV_TOO_MANY_TRACKS) and np.all(r.n_vertices == 0)
+    assert np.all(r.track_vertex == -1)
+    r = oracle.find(b, {"max_vertices": 1})
+    assert np.any(r.status & oracle.EV_VERTEX_OVERFLOW) and np.all(r.n_vertices <= 1)
+    bad = synth.TrackBatch(offsets=np.array([0, 50, 20, b.n_tracks], np.int32),
+                           **{f: getattr(b, f) for f in synth.TRACK_FIELDS})
+    r = oracle.find(bad)
+    assert r.status[1] & oracle.EV_OFFSETS_INVALID
+    x = b.x.copy()
+    x[3] = np.nan
+    b3 = synth.TrackBatch(offsets=b.offsets, **{f: (x if f == "x" else getattr(b, f)) for f in synth.TRACK_FIELDS})
+    r = oracle.find(b3)
+    assert r.status[0] & oracle.EV_NONFINITE_INPUT and r.track_vertex[3] == -1
+
+
+def test_peak_search_boundaries_exact_prominence_and_ties():
+    """A fall and a rise of exactly dip_prom count as significant (Sec. 3.3
+    reading: at least dip_prom); of tied highest bins the first is the peak,
+    and with N_{i+1} = N_i the seed sits half a bin up (Eq. 5 limit)."""
+    U_ = U
+    exact = _hist_from([8000, 7 * U_, 5 * U_, 7 * U_, 8000])
+    cl, _ = oracle.peak_search(exact)
+    assert [(c["lo"], c["hi"]) for c in cl] == [(2000, 2002), (2003, 2004)]
+    under = _hist_from([8000, 7 * U_, 5 * U_ + 1, 7 * U_, 8000])
+    assert len(oracle.peak_search(under)[0]) == 1
+    tie = _hist_from([8000, 5 * U_, 5 * U_, 8000])
+    cl, _ = oracle.peak_search(tie)
+    assert len(cl) == 1 and cl[0]["peak"] == 2001
+    zi = -600 + (2001 + 0.5) * 0.25
+    assert cl[0]["z_seed"] == pytest.approx(zi + 0.125, abs=1e-12)
+
+
+def test_final_selection_beamline_distance_and_regions():
+    """pp vertices farther than 0.3 mm from the beamline are dropped (end of
+    Sec. 3.5); beam-gas vertices are not subject to that cut (Table 2 tunes
+    that region separately).  Probe tracks have tx = 0 so that, with the
+    offset along x, their z_poca is exactly the vertex z; their transverse
+    error (0.18 mm) keeps the offset inside the Tukey window of a seed placed
+    on the beamline."""
+    rng = np.random.default_rng(18)
+
+    def rows_through(P, n):
+        rows = _exact_tracks_through(P, n, rng, dzs=(0.0,))
+        rows[:, 3] = 0.0
+        rows[:, 4] = rng.choice([-0.3125, -0.25, 0.25, 0.3125], n)
+        rows[:, 0] = P[0]
+        rows[:, 5] = 2.0 ** -5
+        return rows
+
+    def nv(P, beam=(0.0, 0.0, 0.0, 0.0)):
+        return oracle.find(synth.from_tracks([rows_through(P, 20)], beamline=beam)).n_vertices[0]
+
+    assert nv((0.25, 0.0, 10.0)) == 1
+    assert nv((0.35, 0.0, 10.0)) == 0
+    assert nv((0.35, 0.0, -400.0)) == 1
+    # tilted beamline: the distance is measured to the beamline at the vertex z
+    assert nv((0.35, 0.0, 100.0), beam=(0.0, 0.0, 0.0035, 0.0)) == 1
