@@ -1,0 +1,206 @@
+"""Benchmark of the primary-vertex finding path on one MI355X.
+
+A step is one pv_find call over the whole batch (every stage of the path:
+projection, histogram, peak search, association, fit, selection) with the
+inputs already resident in HBM.  The default workload is 10,000 synthetic
+events at mu = 5 (pp_mu5_10kev).  One JSON line is printed with events/s,
+the HBM roofline of the main fused kernel (timed with HIP events on its own
+stream), the plain one-launch-per-event rate on the same GPU, and the CPU
+oracle timed on a bounded sample on the host cores.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload pp_mu5_10kev]
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "events/s at mu=5 (batched vs per-event launch); p50/p99 latency in served mode"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_14966_amd", "csrc", "pvfind_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pv_find_hbm_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(n_tracks, n_events, n_vertices):
+    """Bytes a launch must move at minimum: track SoA read once (8 x 4 B),
+    offsets (4 B per event), per-track vertex id + weight (8 B), 64 B per
+    vertex record and 8 B per event (count + status)."""
+    return 32 * n_tracks + 4 * n_events + 8 * n_tracks + 64 * n_vertices + 8 * n_events
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pp_mu5_10kev")
+    ap.add_argument("--per-event-sample", type=int, default=2000,
+                    help="events timed with one launch each (plain form)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="", help="waves,capacity,persistent,teams_per_cu")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so the "
+              f"path shards by event range across GPUs without any exchange; this build measures one GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_14966_amd import pvfind as pv
+    from paper_2412_14966_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    batch = synth.generate(args.workload, keep_truth=False)
+    log(f"generated {batch.n_events} events / {batch.n_tracks} tracks in {time.time() - t0:.1f} s")
+    params = pv.pv_params_default()
+    sched = None
+    if args.schedule:
+        w, c, m, t = (int(v) for v in args.schedule.split(","))
+        sched = pv.pv_schedule(w, c, m, t)
+        pv.pv_set_schedule(w, c, m, t)
+    s = pv.pv_get_schedule()
+    schedule = dict(waves_per_team=s.waves_per_team, track_capacity=s.track_capacity, persistent=s.persistent,
+                    teams_per_cu=s.teams_per_cu)
+
+    db = pv.to_device(batch, dev)
+    out = pv.alloc_outputs(db, params.max_vertices_per_event, dev)
+    stream = torch.cuda.current_stream()
+    L = pv.lib()
+    tr, bl, ov, ot = pv._args(db, out, params)
+    offs = ctypes.c_void_p(db.offsets.data_ptr())
+    st = ctypes.c_void_p(stream.cuda_stream)
+    args_ref = (ctypes.byref(tr), offs, db.n_events, ctypes.byref(bl), ctypes.byref(params), ctypes.byref(ov),
+                ctypes.byref(ot), st)
+
+    def step():
+        rc = L.pv_find(*args_ref)
+        if rc != 0:
+            raise RuntimeError(pv.pv_last_error())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps bracketed by synchronisations
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = batch.n_events / (ms_per_step / 1e3)
+    log(f"batched: {ms_per_step * 1e3:.1f} us per step, {value:.4g} events/s")
+
+    # per-kernel durations of the same steps, from events the library records
+    pv.pv_timing_start()
+    for _ in range(args.steps):
+        step()
+    main_ms, large_ms, ncalls = pv.pv_timing_stop()
+    main_us = main_ms / ncalls * 1e3
+    large_us = large_ms / ncalls * 1e3
+    log(f"main fused kernel {main_us:.1f} us, large-event kernel {large_us:.1f} us per step")
+
+    nv = int(out.n_vertices.sum().item())
+    abytes = algorithmic_bytes(batch.n_tracks, batch.n_events, nv)
+    achieved = abytes / (main_us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tf = json.load(f)
+        if tf.get("kernel_sha") == kernel_hash() and tf.get("workload") == args.workload:
+            traffic = tf.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "pv_find_kernel (main fused launch)", "algorithmic_bytes_per_launch": abytes,
+                "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2)}
+
+    # plain form: one pv_find launch per event on the same stream
+    n_pe = min(args.per_event_sample, batch.n_events)
+    mv = params.max_vertices_per_event
+    base_v, base_n, base_s = out.vertices.data_ptr(), out.n_vertices.data_ptr(), out.status.data_ptr()
+    obase = db.offsets.data_ptr()
+    per_event_args = []
+    for e in range(n_pe):
+        ove = pv.pv_vertices_out(base_v + e * mv * 64, base_n + 4 * e, base_s + 4 * e)
+        per_event_args.append((ove, ctypes.c_void_p(obase + 4 * e)))
+    for e in range(min(50, n_pe)):
+        L.pv_find(ctypes.byref(tr), per_event_args[e][1], 1, ctypes.byref(bl), ctypes.byref(params),
+                  ctypes.byref(per_event_args[e][0]), ctypes.byref(ot), st)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    ev0.record(stream)
+    for e in range(n_pe):
+        rc = L.pv_find(ctypes.byref(tr), per_event_args[e][1], 1, ctypes.byref(bl), ctypes.byref(params),
+                       ctypes.byref(per_event_args[e][0]), ctypes.byref(ot), st)
+        if rc != 0:
+            raise RuntimeError(pv.pv_last_error())
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    host_s = time.perf_counter() - t_host
+    pe_ms = ev0.elapsed_time(ev1)
+    per_event = {"events_per_s": round(n_pe / (pe_ms / 1e3), 1), "events_timed": n_pe,
+                 "us_per_event": round(pe_ms * 1e3 / n_pe, 2), "host_wall_s": round(host_s, 3),
+                 "launches_per_event": 2 if params.max_tracks_per_event > schedule["track_capacity"] else 1,
+                 "batched_speedup": round(value / (n_pe / (pe_ms / 1e3)), 1)}
+    log(f"per-event launches: {per_event['us_per_event']} us/event")
+
+    # CPU oracle on a bounded sample (test infrastructure, timed as a baseline)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        op = oracle.params_from_fields(pv.params_dict(params))
+        threads = oracle.max_threads()
+        done, t1 = 0, time.perf_counter()
+        passes = 0
+        while True:
+            oracle.find(batch, op, n_threads=threads)
+            done += batch.n_events
+            passes += 1
+            if time.perf_counter() - t1 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(done / dt, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+               "sample": f"{passes} pass(es) over the same {batch.n_events}-event workload, "
+                         f"{dt:.1f} s wall, OpenMP over events"}
+        log(f"cpu oracle: {cpu['value']} events/s on {threads} threads")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
+                   "n_vertices": nv, "schedule": schedule},
+        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

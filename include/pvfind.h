@@ -1,0 +1,227 @@
+/*
+ * pvfind.h -- C ABI of libpvfind, primary-vertex finding on AMD Instinct
+ * MI355X (gfx950) after "A parallel algorithm for fast reconstruction of
+ * primary vertices on heterogeneous architectures" (LHCb, arXiv:2412.14966).
+ *
+ * Per event the library runs the five steps of the paper's Sec. 3:
+ *   1. project every track to its point of closest approach to the beamline
+ *      (z_poca, Eq. 1) with uncertainty sigma_poca (Eq. 3);
+ *   2. fill a z histogram in which each track spreads one unit of mass over
+ *      the bins around z_poca (Sec. 3.2);
+ *   3. find proto-clusters, split them at significant minima and place one
+ *      seed per cluster (Sec. 3.3, Eq. 4-5);
+ *   4. associate every track to one cluster through partition points,
+ *      removing clusters with too few tracks (Sec. 3.4);
+ *   5. fit each cluster's vertex with the Tukey-weighted Newton-Raphson fit
+ *      (Sec. 3.5, Eq. 6-17) and apply the final selection (Table 2, end of
+ *      Sec. 3.5).
+ *
+ * Conventions for every entry point:
+ *  - Track, offset and output pointers are DEVICE pointers (HIP device
+ *    memory of the current device).  Structs passed by pointer to an entry
+ *    point (pv_tracks, pv_params, ...) are HOST memory and are read before
+ *    the call returns.
+ *  - The caller owns every buffer.  The library owns only its internal
+ *    workspace (a few KiB per stream, plus 4 bytes per event of the largest
+ *    batch seen) and never frees caller memory.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    default stream); outputs are valid once the caller synchronises it.
+ *    Calls on different streams are independent.  Calls that share a stream
+ *    are serialised by it.
+ *  - Return value: PV_OK (0) or a negative PV_E* code; pv_last_error()
+ *    describes the last failure of the calling thread.  No C++ exception
+ *    crosses this interface.  Problems found on the device in one event
+ *    never abort the batch: they set that event's status bits.
+ */
+#ifndef PVFIND_H
+#define PVFIND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PV_OK        0
+#define PV_EINVAL  (-1)   /* null pointer, negative count, inconsistent parameters */
+#define PV_EHIP    (-2)   /* a HIP runtime call failed                               */
+#define PV_ENOMEM  (-3)   /* workspace allocation failed                             */
+#define PV_EBUSY   (-4)   /* server: no admission possible right now                 */
+
+/* per-event status bits */
+#define PV_EV_NONFINITE_INPUT  1  /* some track had a NaN/Inf field; it was skipped     */
+#define PV_EV_TOO_MANY_TRACKS  2  /* more than max_tracks_per_event; event skipped      */
+#define PV_EV_VERTEX_OVERFLOW  4  /* more seed clusters than max_vertices_per_event;
+                                     the first ones in z were kept                      */
+#define PV_EV_OFFSETS_INVALID  8  /* offsets of this event out of order or range;
+                                     event skipped, its track outputs left untouched    */
+
+/* per-vertex flag bits */
+#define PV_VX_NOT_CONVERGED    1  /* stopped at max_iter (Sec. 3.5 caps the iterations) */
+#define PV_VX_FP64_INVERSION   2  /* covariance inverted in binary64 (ill-conditioned)  */
+
+/* Track states at z_trk (Sec. 2: straight VELO tracks with state x, y,
+ * tx = dx/dz, ty = dy/dz and covariance V).  Structure of arrays, float32,
+ * one entry per track, tracks of event e at [offsets[e], offsets[e+1]).
+ * x and y errors are uncorrelated and of identical magnitude (Sec. 3.1), so
+ * one set (Vxx, Vxtx, Vtxtx) serves both projections. */
+typedef struct {
+    const float *x, *y, *z, *tx, *ty;
+    const float *cov_xx, *cov_xtx, *cov_txtx;
+} pv_tracks;
+
+/* Beamline at z = 0 (Sec. 3: average transverse position and direction). */
+typedef struct {
+    float x, y, tx, ty;
+} pv_beamline;
+
+/* Algorithm parameters; pv_params_default() fills the paper's values where it
+ * gives them (Sec. 3.2, 3.4, 3.5, Table 2) and documented choices elsewhere. */
+typedef struct {
+    float   z_min, z_max, dz;          /* histogram range and bin width (mm)          */
+    float   z_gas;                     /* bins below this z use the p-gas settings     */
+    float   sigma_max_pp, sigma_max_gas; /* max sigma_poca to enter the histogram (mm)  */
+    float   u0;                        /* kernel half-width in units of sigma_poca     */
+    int32_t frac_bits;                 /* one track = 2^frac_bits histogram units      */
+    int32_t proto_thr;                 /* proto-cluster threshold (units, bin > thr)   */
+    int32_t dip_prom;                  /* significance of a minimum/maximum (units)    */
+    int32_t min_int_pp, min_int_gas;   /* min cluster integral (units, Table 2)        */
+    int32_t part_min_pp, part_min_gas; /* min tracks of a partition (Sec. 3.4)         */
+    int32_t pv_min_pp, pv_min_gas;     /* min tracks of a final vertex (Table 2)       */
+    int32_t max_iter;                  /* fit iteration cap (Sec. 3.5)                 */
+    float   chi2_max;                  /* Tukey cut-off (Eq. 17)                       */
+    float   conv_dchi2, conv_dz;       /* convergence: |dchi2| and |dz_vtx| (mm)       */
+    float   max_rho_pp;                /* pp vertices within this distance of the beam */
+    float   cond_fp64;                 /* covariance inverted in binary64 above this
+                                          1-norm condition number                      */
+    float   sing_ratio;                /* the fit fails when the normal matrix has
+                                          det <= sing_ratio * product of its diagonal
+                                          (e.g. a single weighted track)               */
+    int32_t max_tracks_per_event;      /* <= 4096                                      */
+    int32_t max_vertices_per_event;    /* <= 128; output slots per event               */
+} pv_params;
+
+/* One fitted vertex, 64 bytes. */
+typedef struct {
+    float   x, y, z;                   /* mm */
+    float   cov[6];                    /* xx, xy, yy, xz, yz, zz (Eq. 14)              */
+    float   chi2;                      /* sum_i w_i chi2_i at the final position      */
+    float   ndof;                      /* 2 sum_i w_i - 3                              */
+    float   z_seed;                    /* Eq. 4                                        */
+    int32_t n_tracks;                  /* tracks associated through the partition     */
+    int16_t bin_lo, bin_hi;            /* seed cluster bin range                      */
+    int16_t peak_bin;                  /* highest bin of the seed cluster             */
+    uint8_t n_iter;                    /* fit iterations                               */
+    uint8_t flags;                     /* PV_VX_* bits                                 */
+    int32_t reserved;
+} pv_vertex;
+
+typedef struct {
+    pv_vertex *vertices;               /* n_events * max_vertices_per_event slots;
+                                          event e's vertices at e * max_vertices, in z
+                                          order of their seeds                         */
+    int32_t   *n_vertices;             /* n_events                                      */
+    int32_t   *status;                 /* n_events, PV_EV_* bits                        */
+} pv_vertices_out;
+
+/* Per input track: index of its vertex within the event (-1 if none) and its
+ * final Tukey weight (0 if none). */
+typedef struct {
+    int32_t *vertex;
+    float   *weight;
+} pv_track_out;
+
+/* Seed cluster as found by step 3 and treated by step 4 (debug output). */
+typedef struct {
+    int32_t lo, hi, peak;              /* bin range and first highest bin              */
+    float   z_seed;
+    int32_t kept;                      /* 1 if it survived the association step        */
+    int32_t n_assoc;                   /* its tracks after the association step        */
+    int32_t own_lo, own_hi;            /* bins it owns after the association step      */
+} pv_cluster;
+
+/* Optional intermediate results of pv_find_debug; any member may be NULL. */
+typedef struct {
+    int32_t    *hist;                  /* n_events * n_bins fixed-point histogram      */
+    pv_cluster *clusters;              /* n_events * max_vertices_per_event            */
+    int32_t    *n_clusters;            /* n_events: clusters written for the event     */
+    float      *zpoca, *sigma;         /* per track, Eq. 1 and Eq. 3                   */
+    int32_t    *bin;                   /* per track central bin, -1 outside            */
+} pv_debug_out;
+
+/* How a batch is mapped onto the GPU.  Zero fields mean "library choice". */
+typedef struct {
+    int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4 */
+    int32_t track_capacity;            /* tracks per event held in LDS by small teams:
+                                          256, 512 or 1024; larger events go to a
+                                          second launch with 4096-track teams         */
+    int32_t persistent;                /* 1: persistent grid + device work queue;
+                                          2: one team per event, hardware-scheduled    */
+    int32_t teams_per_cu;              /* persistent grid size per compute unit        */
+} pv_schedule;
+
+/* Fill *p with the defaults described above. */
+void pv_params_default(pv_params *p);
+
+/* Number of histogram bins for *p, or -1 if (z_max - z_min) / dz is not a
+ * whole number between 1 and 4096. */
+int32_t pv_nbins(const pv_params *p);
+
+/* The whole path over a batch of events (Sec. 3.1-3.5).
+ *  tracks        : device SoA arrays of offsets[n_events] tracks (float32).
+ *  event_offsets : device int32[n_events + 1]; event e owns tracks
+ *                  [offsets[e], offsets[e+1]); offsets[n_events] is the number
+ *                  of tracks in the arrays.  Events whose offsets are negative,
+ *                  decreasing or beyond offsets[n_events] are flagged
+ *                  PV_EV_OFFSETS_INVALID.
+ *  n_events      : >= 0; 0 enqueues nothing.
+ *  beamline, params : host structs.
+ *  out_vertices  : device outputs, see pv_vertices_out.
+ *  out_track_weights : device outputs, one entry per track.
+ *  stream        : hipStream_t.
+ * The schedule is the library's current default (see pv_set_schedule). */
+int pv_find(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+            const pv_beamline *beamline, const pv_params *params,
+            pv_vertices_out *out_vertices, pv_track_out *out_track_weights, void *stream);
+
+/* pv_find with an explicit schedule (NULL = default).  Integer outputs (vertex
+ * counts, track-to-vertex indices, histograms, clusters) do not depend on
+ * the schedule; floating-point outputs are reproducible bit for bit for a
+ * fixed schedule and agree across schedules to rounding. */
+int pv_find_sched(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                  const pv_beamline *beamline, const pv_params *params,
+                  pv_vertices_out *out_vertices, pv_track_out *out_track_weights,
+                  const pv_schedule *schedule, void *stream);
+
+/* pv_find that also writes the intermediate results named in *debug
+ * (device pointers, NULL members skipped).  Same outputs as pv_find. */
+int pv_find_debug(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                  const pv_beamline *beamline, const pv_params *params,
+                  pv_vertices_out *out_vertices, pv_track_out *out_track_weights,
+                  const pv_debug_out *debug, const pv_schedule *schedule, void *stream);
+
+/* Replace / read the default schedule used by pv_find (process-wide). */
+int pv_set_schedule(const pv_schedule *schedule);
+int pv_get_schedule(pv_schedule *schedule);
+
+/* Benchmark support: time the library's own kernels with HIP events
+ * recorded on the caller's stream around each launch.
+ * pv_timing_start() drops earlier records and makes every later pv_find*
+ * call record events; pv_timing_stop() stops recording, waits for the
+ * recorded events and returns the total milliseconds spent in the main fused
+ * kernel and in the large-event kernel, and the number of calls timed (any
+ * output pointer may be NULL). */
+int pv_timing_start(void);
+int pv_timing_stop(double *main_ms, double *large_ms, int64_t *n_calls);
+
+/* Thread-local description of the last non-zero return of this thread. */
+const char *pv_last_error(void);
+
+/* Library version string. */
+const char *pv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -45,7 +45,7 @@ class OrcParams(ctypes.Structure):
         ("pv_min_gas", ctypes.c_int),
         ("max_iter", ctypes.c_int),
         ("chi2_max", ctypes.c_double), ("conv_dchi2", ctypes.c_double), ("conv_dz", ctypes.c_double),
-        ("max_rho_pp", ctypes.c_double),
+        ("max_rho_pp", ctypes.c_double), ("sing_ratio", ctypes.c_double),
         ("max_tracks", ctypes.c_int), ("max_vertices", ctypes.c_int),
     ]
 
@@ -124,6 +124,23 @@ def make_params(overrides: Optional[Dict[str, float]] = None) -> OrcParams:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+# parameter names of the HIP library that differ from the oracle's
+_LIBRARY_NAMES = {"max_tracks_per_event": "max_tracks", "max_vertices_per_event": "max_vertices"}
+
+
+def params_from_fields(fields: Dict) -> Dict:
+    """Oracle parameters holding the values of a parameter mapping that uses
+    the HIP library's field names (fields the oracle has no use for, such as
+    the binary64-inversion threshold of the GPU, are ignored)."""
+    names = {n for n, _ in OrcParams._fields_}
+    out = {}
+    for k, v in fields.items():
+        k2 = _LIBRARY_NAMES.get(k, k)
+        if k2 in names:
+            out[k2] = v
+    return out
 
 
 def nbins(params: Optional[Dict] = None) -> int:

@@ -63,6 +63,7 @@ void orc_params_default(orc_params *p)
     p->conv_dchi2 = 0.01;            /* Sec. 3.5, x86 criterion */
     p->conv_dz = 0.001;              /* 1 micrometre */
     p->max_rho_pp = 0.3;             /* end of Sec. 3.5 */
+    p->sing_ratio = 1e-4;
     p->max_tracks = 4096;
     p->max_vertices = 128;
 }
@@ -425,15 +426,21 @@ static double tukey(double chi2, double chi2_max)
     return 0.0;
 }
 
-/* general 3x3 inverse by the adjugate; returns 0 if the determinant is not
-   positive (the matrices here are symmetric positive semi-definite) */
-static int inverse3(const double a[3][3], double inv[3][3])
+/* general 3x3 inverse by the adjugate.  Returns 0 if the matrix counts as
+   singular: the paper does not say what happens when the normal matrix is
+   singular (for instance when a single track keeps a nonzero weight, which
+   leaves z undetermined); the reading here is that the fit fails when
+   det(A) <= sing_ratio * A00 A11 A22.  For a symmetric positive semi-definite
+   matrix that ratio lies in [0, 1] (Hadamard's inequality) and does not
+   depend on the scale of A. */
+static int inverse3(const double a[3][3], double inv[3][3], double sing_ratio)
 {
     const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
     const double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
     const double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
     const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
-    if (!(det > 0.0) || !isfinite(det))
+    const double diag = a[0][0] * a[1][1] * a[2][2];
+    if (!(det > 0.0) || !isfinite(det) || !(det > sing_ratio * diag))
         return 0;
     inv[0][0] = c00 / det;
     inv[1][0] = c01 / det;
@@ -477,7 +484,8 @@ static double rel_dist(double q, double t)
  * and |dz_vtx| < conv_dz (x86 criterion), or after max_iter iterations
  * (flagged as not converged, result kept).  C = (Hess / 2)^-1 of the last
  * iteration (Eq. 14); the reported weights and chi2 = sum w_i chi2_i are
- * evaluated at the final alpha, and ndof = 2 sum w - 3.
+ * evaluated at the final alpha, and ndof = 2 sum w - 3.  The fit fails when
+ * no weight is left or the Hessian counts as singular (see inverse3).
  */
 int orc_fit(const float *const trk[8], const int *idx, int n,
             double x_seed, double y_seed, double z_seed, const orc_params *p,
@@ -526,7 +534,7 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
             }
         }
         double hinv[3][3];
-        if (!(sumw > 0.0) || !inverse3(hess, hinv)) {
+        if (!(sumw > 0.0) || !inverse3(hess, hinv, p->sing_ratio)) {
             failed = 1;
             break;
         }
@@ -577,7 +585,7 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
     for (a = 0; a < 3; ++a)
         for (b = 0; b < 3; ++b)
             half[a][b] = 0.5 * hess_last[a][b];
-    if (!inverse3(half, C)) {
+    if (!inverse3(half, C, p->sing_ratio)) {
         free(Wd);
         for (k = 0; k < n; ++k)
             w_out[k] = 0.0;

@@ -55,6 +55,7 @@ typedef struct {
     /* fit (Sec. 3.5) */
     int   max_iter;
     double chi2_max, conv_dchi2, conv_dz, max_rho_pp;
+    double sing_ratio;         /* normal matrix singular below this det / prod(diag) */
     /* capacities */
     int   max_tracks, max_vertices;
 } orc_params;

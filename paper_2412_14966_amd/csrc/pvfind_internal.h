@@ -1,0 +1,77 @@
+// pvfind_internal.h -- definitions shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "pvfind.h"
+
+namespace pvk {
+
+constexpr int kMaxBins = 4096;      // histogram bins held in LDS
+constexpr int kMaxVertices = 128;   // seed clusters / vertices per event
+constexpr int kMaxTracks = 4096;    // tracks per event
+constexpr int kBigWaves = 4;        // wavefronts of a large-event team
+constexpr int kBigCapacity = 4096;  // tracks held in LDS by a large-event team
+
+// per-track flags packed into the LDS track word
+constexpr int kTrHist = 1;
+constexpr int kTrAssoc = 2;
+constexpr int kTrNonfinite = 4;
+
+// Parameters as the kernels use them, derived once on the host.
+struct KParams {
+    float z_min, z_max, dz, u0;
+    float sigma_max_pp, sigma_max_gas;
+    float unit;                 // 2^frac_bits
+    int nb, gas_bin;
+    int proto_thr, dip_prom, min_int_pp, min_int_gas;
+    int part_min_pp, part_min_gas, pv_min_pp, pv_min_gas;
+    int max_iter;
+    float chi2_max, inv_chi2_max, conv_dchi2, conv_dz, max_rho2_pp, cond_fp64, sing_ratio;
+    int max_tracks, max_vertices;
+    float bx, by, btx, bty;
+};
+
+// Device workspace of one stream: work-queue counters and the list of events
+// deferred to the large-team launch.  Counters return to zero at the end of
+// every launch (the last workgroup to finish resets them).
+struct WorkQueue {
+    unsigned int next;          // next event index of the main launch
+    unsigned int done;          // workgroups of the main launch that finished
+    unsigned int n_big;         // events deferred to the large-team launch
+    unsigned int next_big;      // next deferred event
+    unsigned int done_big;      // workgroups of the large-team launch that finished
+    unsigned int pad[11];
+    int big[1];                 // n_events entries
+};
+
+struct KArgs {
+    const float *x, *y, *z, *tx, *ty, *cxx, *cxtx, *ctxtx;
+    const int32_t *offsets;
+    int32_t n_events;
+    pv_vertex *vout;
+    int32_t *nv_out;
+    int32_t *status_out;
+    int32_t *trk_vtx;
+    float *trk_w;
+    int32_t *dbg_hist;
+    pv_cluster *dbg_cl;
+    int32_t *dbg_ncl;
+    float *dbg_zp, *dbg_sg;
+    int32_t *dbg_bin;
+    WorkQueue *wq;
+    KParams p;
+};
+
+// Events recorded around the launches of one call (benchmark timing).
+struct LaunchEvents {
+    void *main_begin = nullptr, *main_end = nullptr;    // hipEvent_t
+    void *large_begin = nullptr, *large_end = nullptr;  // hipEvent_t, unused when no large launch
+    bool large = false;
+};
+
+// Launch one batch on `stream` with schedule `s` (already validated).  With
+// `ev`, events are recorded around the launches.  Returns a hipError_t value.
+int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev);
+
+}  // namespace pvk

@@ -1,0 +1,998 @@
+// pvfind_kernels.hip -- gfx950 kernels of the primary-vertex finding path
+// (arXiv:2412.14966, Sec. 3 and Sec. 5).
+//
+// One fused kernel runs the five steps of Sec. 3 for one event per team of W
+// wavefronts.  In persistent mode a grid sized to the chip pops events from a
+// device work queue; otherwise one workgroup per event is hardware-scheduled.
+// Per event:
+//   clear     the LDS histogram (16 KiB for 4000 bins)
+//   project   coalesced SoA loads, one lane per track, Eq. 1 / Eq. 3 in
+//             binary32 with correctly rounded division and square root and
+//             no contraction (the file is built with -ffp-contract=off), so
+//             z_poca, sigma_poca and the central bin are bit-reproducible
+//   fill      integer fixed-point kernel masses added with LDS atomics: the
+//             histogram does not depend on the order of the adds; a 64-bit
+//             mask records which 64-bin words were touched
+//   peaks     wavefront ballots over the touched words give the proto-cluster
+//             runs (bit tricks on the masks), then one lane per proto-cluster
+//             walks the dip search and z-ordered splitting; clusters are
+//             compacted in z order with a wavefront scan
+//   associate partition points, per-track owner by binary search, LDS
+//             counters, removal of the weakest cluster until all pass
+//   gather    stable compaction of the tracks by vertex into LDS arrays that
+//             reuse the histogram's space; positions are stored relative to
+//             the beamline point at the centre of the seed's peak bin (exact
+//             in binary32), so the fit works on small numbers and starts at
+//             the seed offset delta dz without rounding the seed itself
+//   fit       a power-of-two group of lanes per vertex, sums reduced with
+//             butterflies; the 3x3 Newton step is solved by eliminating x and
+//             y (the normal matrix has zeros at (x, y)); covariance inverted
+//             in binary64 only when its 1-norm condition number is large
+//   select    Table 2 minimum tracks and the beamline-distance cut, prefix
+//             compaction of the kept vertices, final weights per track
+// Events with more tracks than a small team holds go to a second launch with
+// four-wavefront teams holding 4096 tracks.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <math.h>
+
+#include "pvfind_internal.h"
+
+namespace pvk {
+
+template <int W, int CAP>
+struct __align__(16) Smem {
+    union {
+        int hist[kMaxBins];
+        struct {
+            float X[CAP];    // track x at the seed z, relative to the seed
+            float Y[CAP];
+            float TX[CAP];
+            float TY[CAP];
+            float WT[CAP];   // 1 / V_x at the seed (Eq. 2), 0 for unusable tracks
+            int IDX[CAP];    // track index within the event
+        } f;
+    } u;
+    int tb[CAP];             // (bin + 1) | flags << 13 | (owner + 1) << 16
+    short clo[kMaxVertices], chi[kMaxVertices], cpk[kMaxVertices];
+    float cd0[kMaxVertices]; // seed offset delta * dz from the centre of the peak bin (Eq. 4)
+    short live[kMaxVertices];
+    int pb[kMaxVertices];    // last bin owned by live slot k
+    int cnt[kMaxVertices];   // tracks owned by live slot k
+    int base[kMaxVertices];  // first gathered slot of live slot k
+    int wrun[W][kMaxVertices];
+    float vdx[kMaxVertices], vdy[kMaxVertices], vdz[kMaxVertices];
+    float va[kMaxVertices], vb[kMaxVertices], vc[kMaxVertices], vd[kMaxVertices];
+    int vinfo[kMaxVertices]; // n_iter | not_converged << 8 | failed << 9
+    int vout[kMaxVertices];
+    short ps[64], pe[64];    // pending proto-clusters
+    unsigned long long occ;
+    int ev, status, n_cl, n_live, done, n_keep;
+};
+
+constexpr int kInfoNotConv = 1 << 8;
+constexpr int kInfoFailed = 1 << 9;
+
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
+{
+    return (1ull << lane) - 1ull;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off)
+            v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ float group_sum(float v, int L)
+{
+    for (int off = 1; off < L; off <<= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.1: projection to the point of closest approach (Eq. 1, Eq. 3)
+// ---------------------------------------------------------------------------
+struct Proj {
+    float zp, sg;
+    int bin, fl;
+};
+
+__device__ __forceinline__ Proj project(float x, float y, float z, float tx, float ty, float vxx,
+                                        float vxtx, float vtxtx, const KParams &p)
+{
+    Proj r{0.0f, 0.0f, -1, 0};
+    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(tx) && isfinite(ty) && isfinite(vxx) &&
+          isfinite(vxtx) && isfinite(vtxtx))) {
+        r.fl = kTrNonfinite;
+        return r;
+    }
+    const float dtx = tx - p.btx;
+    const float dty = ty - p.bty;
+    const float dx = p.bx - x;
+    const float dy = p.by - y;
+    const float num = dtx * dx + dty * dy;
+    const float den = dtx * dtx + dty * dty;
+    if (!(den > 0.0f) || !(vxx > 0.0f))
+        return r;
+    const float zp = z + num / den;
+    const float s2 = vxx / den;
+    const float sg = sqrtf(s2);
+    r.zp = zp;
+    r.sg = sg;
+    if (!(zp >= p.z_min && zp < p.z_max))
+        return r;
+    int b = (int)floorf((zp - p.z_min) / p.dz);
+    b = min(max(b, 0), p.nb - 1);
+    r.bin = b;
+    r.fl = kTrAssoc;
+    const float smax = (b < p.gas_bin) ? p.sigma_max_gas : p.sigma_max_pp;
+    const float sw = p.u0 * sg;
+    if (s2 <= smax * smax && sw > 0.0f)
+        r.fl |= kTrHist;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.2: kernel mass left of a bin edge, cubic cumulative, fixed point
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int edge_code(float e, float zp, float sw, float unit)
+{
+    float s = (e - zp) / sw;
+    if (s < -1.0f)
+        s = -1.0f;
+    if (s > 1.0f)
+        s = 1.0f;
+    const float P = 0.5f + s * (0.75f - 0.25f * (s * s));
+    return (int)rintf(P * unit);
+}
+
+__device__ __forceinline__ void fill_track(int *hist, unsigned long long *occ, float zp, float sw,
+                                           const KParams &p)
+{
+    // any superset of the kernel's support gives the same integers
+    const float fl = fmaxf(floorf((zp - sw - p.z_min) / p.dz) - 1.0f, 0.0f);
+    const float fh = fminf(ceilf((zp + sw - p.z_min) / p.dz) + 1.0f, (float)p.nb);
+    const int jl = (int)fl, jh = (int)fh;
+    if (jh <= jl)
+        return;
+    const int full = (int)p.unit;
+    int prev = (jl == 0) ? 0 : edge_code(p.z_min + (float)jl * p.dz, zp, sw, p.unit);
+    for (int j = jl; j < jh; ++j) {
+        const int next = (j + 1 == p.nb) ? full : edge_code(p.z_min + (float)(j + 1) * p.dz, zp, sw, p.unit);
+        const int d = next - prev;
+        if (d != 0)
+            atomicAdd(&hist[j], d);
+        prev = next;
+    }
+    const int wl = jl >> 6, wh = (jh - 1) >> 6;
+    atomicOr(occ, (2ull << wh) - (1ull << wl));
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e].
+// Returns the number of clusters; with `write` stores them from index `first`.
+// ---------------------------------------------------------------------------
+template <int W, int CAP>
+__device__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, bool write, int first)
+{
+    const int *h = S.u.hist;
+    const bool strad = (s < p.gas_bin) && (e >= p.gas_bin);
+    const int ifix = (s < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
+    auto thr = [&](int lo, int hi) -> int {
+        if (!strad)
+            return ifix;
+        int im = lo;
+        for (int k = lo + 1; k <= hi; ++k)
+            if (h[k] > h[im])
+                im = k;
+        return (im < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
+    };
+    int tot = 0;
+    for (int k = s; k <= e; ++k)
+        tot += h[k];
+    int count = 0;
+    auto emit = [&](int lo, int hi) {
+        if (write) {
+            const int q = first + count;
+            if (q < p.max_vertices) {
+                S.clo[q] = (short)lo;
+                S.chi[q] = (short)hi;
+            }
+        }
+        ++count;
+    };
+    int cs = s, pcs = 0;
+    int up = 1, M = h[s], m = 0, mj = s, pm = 0, pref = h[s];
+    for (int k = s + 1; k <= e; ++k) {
+        const int hk = h[k];
+        pref += hk;
+        if (up) {
+            if (hk > M) {
+                M = hk;
+            } else if (hk <= M - p.dip_prom) {
+                up = 0;
+                m = hk;
+                mj = k;
+                pm = pref;
+            }
+        } else {
+            if (hk < m) {
+                m = hk;
+                mj = k;
+                pm = pref;
+            } else if (hk >= m + p.dip_prom) {
+                if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
+                    emit(cs, mj);
+                    cs = mj + 1;
+                    pcs = pm;
+                }
+                up = 1;
+                M = hk;
+            }
+        }
+    }
+    if (tot - pcs >= thr(cs, e))
+        emit(cs, e);
+    return count;
+}
+
+// Whole peak search, run by wavefront 0.
+template <int W, int CAP>
+__device__ void peak_search(Smem<W, CAP> &S, const KParams &p)
+{
+    const int lane = threadIdx.x & 63;
+    int n_found = 0, npend = 0, open_s = -1, prev_w = -2;
+
+    auto flush = [&]() {
+        const bool has = lane < npend;
+        int s = 0, e = 0;
+        if (has) {
+            s = S.ps[lane];
+            e = S.pe[lane];
+        }
+        const int c = has ? walk_proto(S, p, s, e, false, 0) : 0;
+        const int incl = wave_incl_scan(c, lane);
+        if (has)
+            walk_proto(S, p, s, e, true, n_found + incl - c);
+        n_found += __shfl(incl, 63);
+        npend = 0;
+        __builtin_amdgcn_wave_barrier();
+    };
+    auto push = [&](int s, int e) {
+        if (lane == 0) {
+            S.ps[npend] = (short)s;
+            S.pe[npend] = (short)e;
+        }
+        __builtin_amdgcn_wave_barrier();
+        ++npend;
+        if (npend == 64)
+            flush();
+    };
+
+    unsigned long long occ = S.occ;
+    while (occ) {
+        const int w = __ffsll((long long)occ) - 1;
+        occ &= occ - 1ull;
+        if (open_s >= 0 && prev_w != w - 1) {
+            push(open_s, 64 * prev_w + 63);
+            open_s = -1;
+        }
+        const int j = 64 * w + lane;
+        const int hv = (j < p.nb) ? S.u.hist[j] : 0;
+        const unsigned long long m = __ballot(hv > p.proto_thr);
+        unsigned long long st = m & ~(m << 1);
+        unsigned long long en = m & ~(m >> 1);
+        int cur = -1;
+        if (open_s >= 0) {
+            if (m & 1ull) {
+                cur = open_s;
+                st &= ~1ull;
+            } else {
+                push(open_s, 64 * w - 1);
+            }
+            open_s = -1;
+        }
+        while (en) {
+            const int eb = __ffsll((long long)en) - 1;
+            en &= en - 1ull;
+            if (cur < 0) {
+                const int sb = __ffsll((long long)st) - 1;
+                st &= st - 1ull;
+                cur = 64 * w + sb;
+            }
+            if (eb == 63)
+                open_s = cur;
+            else
+                push(cur, 64 * w + eb);
+            cur = -1;
+        }
+        prev_w = w;
+    }
+    if (open_s >= 0)
+        push(open_s, 64 * prev_w + 63);
+    if (npend > 0)
+        flush();
+
+    const int ncl = min(n_found, p.max_vertices);
+    // seeds (Eq. 4-5): first highest bin, parabola-like correction from the neighbours
+    for (int q = lane; q < ncl; q += 64) {
+        const int lo = S.clo[q], hi = S.chi[q];
+        const int *h = S.u.hist;
+        int im = lo;
+        for (int k = lo + 1; k <= hi; ++k)
+            if (h[k] > h[im])
+                im = k;
+        const int Ni = h[im];
+        const int Nm = (im > 0) ? h[im - 1] : 0;
+        const int Np = (im + 1 < p.nb) ? h[im + 1] : 0;
+        const int den = 2 * Ni - Np - Nm;
+        float delta = (den > 0) ? 0.5f * (float)(Np - Nm) / (float)den : 0.0f;
+        delta = fminf(fmaxf(delta, -0.5f), 0.5f);
+        S.cpk[q] = (short)im;
+        S.cd0[q] = delta * p.dz;
+    }
+    if (lane == 0) {
+        S.n_cl = ncl;
+        if (n_found > p.max_vertices)
+            S.status |= PV_EV_VERTEX_OVERFLOW;
+    }
+}
+
+// centre of bin i, z_i of Eq. 4; the fit's frame is anchored there because
+// z_i is exact in binary32 for the usual ranges while z_seed is not
+__device__ __forceinline__ float bin_centre(int i, const KParams &p)
+{
+    return p.z_min + ((float)i + 0.5f) * p.dz;
+}
+
+__device__ __forceinline__ int lower_bound_bins(const int *pb, int n, int bin)
+{
+    int lo = 0, hi = n - 1;   // pb[n-1] >= every bin
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pb[mid] >= bin)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// 3x3 covariance C = A^-1 for A = [[a, 0, -b], [0, a, -c], [-b, -c, d]] (Eq. 14).
+template <typename T>
+__device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
+{
+    const T D = a * d - b * b - c * c;
+    const T det = a * D;
+    const T r = T(1) / det;
+    out[0] = (a * d - c * c) * r;   // xx
+    out[1] = (b * c) * r;           // xy
+    out[2] = (a * d - b * b) * r;   // yy
+    out[3] = (a * b) * r;           // xz
+    out[4] = (a * c) * r;           // yz
+    out[5] = (a * a) * r;           // zz
+    return det;
+}
+
+// ---------------------------------------------------------------------------
+// one event
+// ---------------------------------------------------------------------------
+template <int W, int CAP, bool BIG, bool DEBUG>
+__device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
+{
+    constexpr int NT = 64 * W;
+    const KParams &p = A.p;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    const int a = A.offsets[e], b = A.offsets[e + 1], total = A.offsets[A.n_events];
+    const bool bad_offsets = (a < 0) || (b < a) || (b > total);
+    const int n = bad_offsets ? 0 : b - a;
+    if (bad_offsets || n > p.max_tracks) {
+        if (!bad_offsets) {
+            for (int i = tid; i < n; i += NT) {
+                A.trk_vtx[a + i] = -1;
+                A.trk_w[a + i] = 0.0f;
+            }
+        }
+        if (DEBUG && A.dbg_hist)
+            for (int j = tid; j < p.nb; j += NT)
+                A.dbg_hist[(size_t)e * p.nb + j] = 0;
+        if (tid == 0) {
+            A.status_out[e] = bad_offsets ? PV_EV_OFFSETS_INVALID : PV_EV_TOO_MANY_TRACKS;
+            A.nv_out[e] = 0;
+            if (DEBUG && A.dbg_ncl)
+                A.dbg_ncl[e] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    if (!BIG && n > CAP) {
+        if (tid == 0) {
+            const unsigned int k = atomicAdd(&A.wq->n_big, 1u);
+            A.wq->big[k] = e;
+        }
+        __syncthreads();
+        return;
+    }
+
+    // clear
+    {
+        int4 *h4 = reinterpret_cast<int4 *>(S.u.hist);
+        const int n4 = (p.nb + 3) >> 2;
+        for (int i = tid; i < n4; i += NT)
+            h4[i] = make_int4(0, 0, 0, 0);
+        if (tid == 0) {
+            S.occ = 0ull;
+            S.status = 0;
+            S.done = 0;
+        }
+    }
+    __syncthreads();
+
+    // project + fill
+    for (int i = tid; i < n; i += NT) {
+        const int g = a + i;
+        const Proj r = project(A.x[g], A.y[g], A.z[g], A.tx[g], A.ty[g], A.cxx[g], A.cxtx[g], A.ctxtx[g], p);
+        if (r.fl & kTrNonfinite)
+            atomicOr(&S.status, PV_EV_NONFINITE_INPUT);
+        if (r.fl & kTrHist)
+            fill_track(S.u.hist, &S.occ, r.zp, p.u0 * r.sg, p);
+        S.tb[i] = (r.bin + 1) | (r.fl << 13);
+        if (DEBUG) {
+            if (A.dbg_zp)
+                A.dbg_zp[g] = r.zp;
+            if (A.dbg_sg)
+                A.dbg_sg[g] = r.sg;
+            if (A.dbg_bin)
+                A.dbg_bin[g] = r.bin;
+        }
+    }
+    __syncthreads();
+    if (DEBUG && A.dbg_hist)
+        for (int j = tid; j < p.nb; j += NT)
+            A.dbg_hist[(size_t)e * p.nb + j] = S.u.hist[j];
+
+    // peaks and seeds
+    if (wave == 0)
+        peak_search(S, p);
+    __syncthreads();
+
+    // association with iterative removal (Sec. 3.4)
+    if (wave == 0) {
+        for (int q = lane; q < S.n_cl; q += 64)
+            S.live[q] = (short)q;
+        if (lane == 0)
+            S.n_live = S.n_cl;
+    }
+    __syncthreads();
+    for (;;) {
+        const int nl = S.n_live;
+        if (wave == 0) {
+            for (int k = lane; k < nl; k += 64) {
+                const int cq = S.live[k];
+                S.pb[k] = (k + 1 < nl) ? ((S.chi[cq] + S.clo[S.live[k + 1]]) >> 1) : p.nb - 1;
+                S.cnt[k] = 0;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+            const int t = S.tb[i];
+            int own = -1;
+            if (((t >> 13) & kTrAssoc) && nl > 0) {
+                own = lower_bound_bins(S.pb, nl, (t & 0x1FFF) - 1);
+                atomicAdd(&S.cnt[own], 1);
+            }
+            S.tb[i] = (t & 0xFFFF) | ((own + 1) << 16);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            int key = INT_MAX;
+            for (int k = lane; k < nl; k += 64) {
+                const int cq = S.live[k];
+                const int need = (S.cpk[cq] < p.gas_bin) ? p.part_min_gas : p.part_min_pp;
+                const int c = S.cnt[k];
+                if (c < need)
+                    key = min(key, (c << 8) | k);
+            }
+            key = wave_min(key);
+            if (key == INT_MAX) {
+                if (lane == 0)
+                    S.done = 1;
+            } else {
+                const int kv = key & 0xFF;
+                const int k0 = lane, k1 = lane + 64;
+                short v0 = 0, v1 = 0;
+                if (k0 < nl - 1)
+                    v0 = S.live[k0 + (k0 >= kv ? 1 : 0)];
+                if (k1 < nl - 1)
+                    v1 = S.live[k1 + (k1 >= kv ? 1 : 0)];
+                __builtin_amdgcn_wave_barrier();
+                if (k0 < nl - 1)
+                    S.live[k0] = v0;
+                if (k1 < nl - 1)
+                    S.live[k1] = v1;
+                if (lane == 0)
+                    S.n_live = nl - 1;
+            }
+        }
+        __syncthreads();
+        if (S.done)
+            break;
+    }
+    const int nl = S.n_live;
+
+    if (DEBUG && A.dbg_cl && wave == 0) {
+        for (int q = lane; q < S.n_cl; q += 64)
+            S.vout[q] = -1;
+        __builtin_amdgcn_wave_barrier();
+        for (int k = lane; k < nl; k += 64)
+            S.vout[S.live[k]] = k;
+        __builtin_amdgcn_wave_barrier();
+        for (int q = lane; q < S.n_cl; q += 64) {
+            const int k = S.vout[q];
+            pv_cluster c;
+            c.lo = S.clo[q];
+            c.hi = S.chi[q];
+            c.peak = S.cpk[q];
+            c.z_seed = bin_centre(S.cpk[q], p) + S.cd0[q];
+            c.kept = (k >= 0) ? 1 : 0;
+            c.n_assoc = (k >= 0) ? S.cnt[k] : 0;
+            c.own_lo = (k > 0) ? S.pb[k - 1] + 1 : (k == 0 ? 0 : -1);
+            c.own_hi = (k >= 0) ? S.pb[k] : -1;
+            A.dbg_cl[(size_t)e * p.max_vertices + q] = c;
+        }
+    }
+
+    // gather tracks by vertex (stable, by track index)
+    if (wave == 0) {
+        const int c0 = (lane < nl) ? S.cnt[lane] : 0;
+        const int c1 = (lane + 64 < nl) ? S.cnt[lane + 64] : 0;
+        const int i0 = wave_incl_scan(c0, lane);
+        const int t0 = __shfl(i0, 63);
+        const int i1 = wave_incl_scan(c1, lane);
+        if (lane < nl)
+            S.base[lane] = i0 - c0;
+        if (lane + 64 < nl)
+            S.base[lane + 64] = t0 + i1 - c1;
+    }
+    const int R = (((n + W - 1) / W) + 63) & ~63;
+    const int r0 = wave * R, r1 = min(n, r0 + R);
+    if (W > 1) {
+        for (int k = tid; k < W * kMaxVertices; k += NT)
+            (&S.wrun[0][0])[k] = 0;
+        __syncthreads();
+        for (int i = r0 + lane; i < r1; i += 64) {
+            const int own = (S.tb[i] >> 16) - 1;
+            if (own >= 0)
+                atomicAdd(&S.wrun[wave][own], 1);
+        }
+        __syncthreads();
+        for (int k = tid; k < nl; k += NT) {
+            int run = S.base[k];
+            for (int w = 0; w < W; ++w) {
+                const int t = S.wrun[w][k];
+                S.wrun[w][k] = run;
+                run += t;
+            }
+        }
+        __syncthreads();
+    } else {
+        __syncthreads();
+        for (int k = tid; k < nl; k += NT)
+            S.wrun[0][k] = S.base[k];
+        __syncthreads();
+    }
+    for (int c0 = r0; c0 < r1; c0 += 64) {
+        const int i = c0 + lane;
+        const bool valid = i < r1;
+        const int own = valid ? (S.tb[i] >> 16) - 1 : -1;
+        unsigned long long rem = __ballot(own >= 0);
+        int slot = -1;
+        while (rem) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const int ol = __shfl(own, leader);
+            const unsigned long long mm = __ballot(own == ol);
+            if (own == ol)
+                slot = S.wrun[wave][ol] + __popcll(mm & lanemask_lt(lane));
+            __builtin_amdgcn_wave_barrier();
+            if (lane == leader)
+                S.wrun[wave][ol] += __popcll(mm);
+            __builtin_amdgcn_wave_barrier();
+            rem &= ~mm;
+        }
+        if (valid) {
+            const int g = a + i;
+            if (slot >= 0) {
+                const float x = A.x[g], y = A.y[g], z = A.z[g], tx = A.tx[g], ty = A.ty[g];
+                const float vxx = A.cxx[g], vxtx = A.cxtx[g], vtxtx = A.ctxtx[g];
+                // positions relative to the beamline point at the peak-bin centre
+                const int cq = S.live[own];
+                const float zr = bin_centre(S.cpk[cq], p);
+                const float dzr = zr - z;
+                S.u.f.X[slot] = fmaf(dzr, tx, x) - (p.bx + p.btx * zr);
+                S.u.f.Y[slot] = fmaf(dzr, ty, y) - (p.by + p.bty * zr);
+                S.u.f.TX[slot] = tx;
+                S.u.f.TY[slot] = ty;
+                // Eq. 2 at the seed: z_seed - z_trk = (z_i - z_trk) + delta dz
+                const float dzs = dzr + S.cd0[cq];
+                const float V = fmaf(dzs, fmaf(dzs, vtxtx, 2.0f * vxtx), vxx);
+                S.u.f.WT[slot] = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
+                S.u.f.IDX[slot] = i;
+            } else {
+                A.trk_vtx[g] = -1;
+                A.trk_w[g] = 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+
+    // fit (Sec. 3.5): L lanes per vertex
+    int L = 64;
+    {
+        const int target = NT / max(nl, 1);
+        while (L > 1 && L > target)
+            L >>= 1;
+    }
+    const int G = NT / L;
+    const int gid = tid / L, gl = tid & (L - 1);
+    for (int k0 = 0; k0 < nl; k0 += G) {
+        const int k = k0 + gid;
+        const bool has = k < nl;
+        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+        // start at the seed: on the beamline, delta dz above the bin centre
+        const float d0 = has ? S.cd0[S.live[k]] : 0.0f;
+        float dx = p.btx * d0, dy = p.bty * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f, ld = 0.0f;
+        int nit = 0;
+        bool active = has, failed = false, conv = false;
+        for (int it = 1; it <= p.max_iter; ++it) {
+            if (!__any(active))
+                break;
+            float s0 = 0.0f, sx = 0.0f, sy = 0.0f, szz = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f, sw = 0.0f;
+            if (active) {
+                for (int t = gl; t < ck; t += L) {
+                    const int sl = beg + t;
+                    const float wt = S.u.f.WT[sl];
+                    if (!(wt > 0.0f))
+                        continue;
+                    const float tx = S.u.f.TX[sl], ty = S.u.f.TY[sl];
+                    const float rx = fmaf(dz, tx, S.u.f.X[sl]) - dx;
+                    const float ry = fmaf(dz, ty, S.u.f.Y[sl]) - dy;
+                    const float chi2 = wt * fmaf(rx, rx, ry * ry);
+                    if (chi2 < p.chi2_max) {
+                        const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
+                        const float w = u * u;
+                        const float ww = w * wt;
+                        sw += w;
+                        s0 += ww;
+                        sx = fmaf(ww, tx, sx);
+                        sy = fmaf(ww, ty, sy);
+                        szz = fmaf(ww, fmaf(tx, tx, ty * ty), szz);
+                        const float px = ww * rx, py = ww * ry;
+                        gx += px;
+                        gy += py;
+                        gz = fmaf(px, tx, fmaf(py, ty, gz));
+                    }
+                }
+            }
+            s0 = group_sum(s0, L);
+            sx = group_sum(sx, L);
+            sy = group_sum(sy, L);
+            szz = group_sum(szz, L);
+            gx = group_sum(gx, L);
+            gy = group_sum(gy, L);
+            gz = group_sum(gz, L);
+            sw = group_sum(sw, L);
+            if (active) {
+                // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz)
+                // det(A) = s0 * D; singular when det <= sing_ratio * s0 * s0 * szz
+                const float D = fmaf(s0, szz, -fmaf(sx, sx, sy * sy));
+                if (!(sw > 0.0f) || !(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
+                    failed = true;
+                    active = false;
+                } else {
+                    const float ddz = fmaf(sx, gx, fmaf(sy, gy, -s0 * gz)) / D;
+                    const float ddx = fmaf(sx, ddz, gx) / s0;
+                    const float ddy = fmaf(sy, ddz, gy) / s0;
+                    const float dchi2 = fmaf(ddz, gz, -fmaf(ddx, gx, ddy * gy));
+                    dx += ddx;
+                    dy += ddy;
+                    dz += ddz;
+                    la = s0;
+                    lb = sx;
+                    lc = sy;
+                    ld = szz;
+                    nit = it;
+                    if (fabsf(dchi2) < p.conv_dchi2 && fabsf(ddz) < p.conv_dz) {
+                        conv = true;
+                        active = false;
+                    }
+                }
+            }
+        }
+        if (has && gl == 0) {
+            S.vdx[k] = dx;
+            S.vdy[k] = dy;
+            S.vdz[k] = dz;
+            S.va[k] = la;
+            S.vb[k] = lb;
+            S.vc[k] = lc;
+            S.vd[k] = ld;
+            S.vinfo[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
+        }
+    }
+    __syncthreads();
+
+    // final selection (Table 2, end of Sec. 3.5)
+    if (wave == 0) {
+        int kept = 0;
+        for (int k0 = 0; k0 < nl; k0 += 64) {
+            const int k = k0 + lane;
+            bool keep = false;
+            if (k < nl) {
+                const int cq = S.live[k];
+                const bool gas = S.cpk[cq] < p.gas_bin;
+                keep = !(S.vinfo[k] & kInfoFailed) && S.cnt[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
+                if (keep && !gas) {
+                    const float zr = bin_centre(S.cpk[cq], p);
+                    const float zv = zr + S.vdz[k];
+                    const float xv = (p.bx + p.btx * zr) + S.vdx[k];
+                    const float yv = (p.by + p.bty * zr) + S.vdy[k];
+                    const float rx = xv - (p.bx + p.btx * zv);
+                    const float ry = yv - (p.by + p.bty * zv);
+                    keep = fmaf(rx, rx, ry * ry) <= p.max_rho2_pp;
+                }
+            }
+            const unsigned long long km = __ballot(keep);
+            if (k < nl)
+                S.vout[k] = keep ? kept + __popcll(km & lanemask_lt(lane)) : -1;
+            kept += __popcll(km);
+        }
+        if (lane == 0)
+            S.n_keep = kept;
+    }
+    __syncthreads();
+
+    // final weights, vertex records
+    for (int k0 = 0; k0 < nl; k0 += G) {
+        const int k = k0 + gid;
+        const bool has = k < nl;
+        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+        const int vo = has ? S.vout[k] : -1;
+        const float dx = has ? S.vdx[k] : 0.0f, dy = has ? S.vdy[k] : 0.0f, dz = has ? S.vdz[k] : 0.0f;
+        float schi = 0.0f, sw = 0.0f;
+        for (int t = gl; t < ck; t += L) {
+            const int sl = beg + t;
+            const float wt = S.u.f.WT[sl];
+            float w = 0.0f, chi2 = 0.0f;
+            if (wt > 0.0f) {
+                const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
+                const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
+                chi2 = wt * fmaf(rx, rx, ry * ry);
+                if (chi2 < p.chi2_max) {
+                    const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
+                    w = u * u;
+                }
+            }
+            schi = fmaf(w, chi2, schi);
+            sw += w;
+            const int g = a + S.u.f.IDX[sl];
+            A.trk_vtx[g] = vo;
+            A.trk_w[g] = (vo >= 0) ? w : 0.0f;
+        }
+        schi = group_sum(schi, L);
+        sw = group_sum(sw, L);
+        if (has && gl == 0 && vo >= 0) {
+            const int cq = S.live[k];
+            const float zr = bin_centre(S.cpk[cq], p);
+            const float la = S.va[k], lb = S.vb[k], lc = S.vc[k], ld = S.vd[k];
+            float cf[6];
+            const float det = inverse_a<float>(la, lb, lc, ld, cf);
+            // 1-norm condition number of A
+            const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
+            const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
+                                         fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
+                                   fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
+            int flags = (S.vinfo[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
+            if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
+                double cd[6];
+                inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
+                for (int q = 0; q < 6; ++q)
+                    cf[q] = (float)cd[q];
+                flags |= PV_VX_FP64_INVERSION;
+            }
+            pv_vertex v;
+            v.x = (p.bx + p.btx * zr) + dx;
+            v.y = (p.by + p.bty * zr) + dy;
+            v.z = zr + dz;
+            for (int q = 0; q < 6; ++q)
+                v.cov[q] = cf[q];
+            v.chi2 = schi;
+            v.ndof = 2.0f * sw - 3.0f;
+            v.z_seed = zr + S.cd0[cq];
+            v.n_tracks = S.cnt[k];
+            v.bin_lo = S.clo[cq];
+            v.bin_hi = S.chi[cq];
+            v.peak_bin = S.cpk[cq];
+            v.n_iter = (uint8_t)(S.vinfo[k] & 0xFF);
+            v.flags = (uint8_t)flags;
+            v.reserved = 0;
+            A.vout[(size_t)e * p.max_vertices + vo] = v;
+        }
+    }
+    if (tid == 0) {
+        A.nv_out[e] = S.n_keep;
+        A.status_out[e] = S.status;
+        if (DEBUG && A.dbg_ncl)
+            A.dbg_ncl[e] = S.n_cl;
+    }
+    __syncthreads();
+}
+
+// mode 0: one workgroup per event (grid = n_events); mode 1: persistent grid
+// with a device work queue.  BIG kernels always take the deferred-event queue.
+template <int W, int CAP, bool BIG, bool DEBUG>
+__global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
+{
+    __shared__ Smem<W, CAP> S;
+    const int tid = threadIdx.x;
+    bool first = true;
+    for (;;) {
+        if (tid == 0) {
+            int e = -1;
+            if (BIG) {
+                const unsigned int k = atomicAdd(&A.wq->next_big, 1u);
+                const unsigned int nbig = atomicAdd(&A.wq->n_big, 0u);
+                if (k < nbig)
+                    e = A.wq->big[k];
+            } else if (mode == 1) {
+                const unsigned int k = atomicAdd(&A.wq->next, 1u);
+                if (k < (unsigned int)A.n_events)
+                    e = (int)k;
+            } else if (first) {
+                e = (int)blockIdx.x;
+            }
+            S.ev = e;
+        }
+        first = false;
+        __syncthreads();
+        const int e = S.ev;
+        __syncthreads();
+        if (e < 0)
+            break;
+        process_event<W, CAP, BIG, DEBUG>(S, A, e);
+    }
+    if (tid == 0 && (BIG || mode == 1)) {
+        __threadfence();
+        unsigned int *done = BIG ? &A.wq->done_big : &A.wq->done;
+        const unsigned int prev = atomicAdd(done, 1u);
+        if (prev == gridDim.x - 1) {
+            if (BIG) {
+                atomicExch(&A.wq->next_big, 0u);
+                atomicExch(&A.wq->n_big, 0u);
+                atomicExch(&A.wq->done_big, 0u);
+            } else {
+                atomicExch(&A.wq->next, 0u);
+                atomicExch(&A.wq->done, 0u);
+            }
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct DevInfo {
+    int cus = 0;
+};
+
+static int device_cus()
+{
+    static int cached_dev = -1, cached_cus = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    if (dev != cached_dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached_dev = dev;
+        cached_cus = cus;
+    }
+    return cached_cus;
+}
+
+template <int W, int CAP, bool BIG, bool DEBUG>
+static hipError_t launch_one(const KArgs &A, int mode, int teams_per_cu, hipStream_t st)
+{
+    auto *fn = pv_find_kernel<W, CAP, BIG, DEBUG>;
+    int grid;
+    if (mode == 1 || BIG) {
+        int occ = 0;
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * W, 0);
+        if (err != hipSuccess)
+            return err;
+        if (occ < 1)
+            occ = 1;
+        if (teams_per_cu > 0 && teams_per_cu < occ)
+            occ = teams_per_cu;
+        const int cus = device_cus();
+        grid = occ * (cus > 0 ? cus : 256);
+        if (!BIG && grid > A.n_events)
+            grid = A.n_events;
+        if (grid < 1)
+            grid = 1;
+    } else {
+        grid = A.n_events;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * W), 0, st, A, BIG ? 1 : mode);
+    return hipGetLastError();
+}
+
+static hipError_t record(void *ev, hipStream_t st)
+{
+    return ev ? hipEventRecord(reinterpret_cast<hipEvent_t>(ev), st) : hipSuccess;
+}
+
+template <int W, int CAP, bool DEBUG>
+static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
+{
+    hipError_t err = record(ev ? ev->main_begin : nullptr, st);
+    if (err == hipSuccess)
+        err = launch_one<W, CAP, false, DEBUG>(A, s.persistent == 1 ? 1 : 0, s.teams_per_cu, st);
+    if (err == hipSuccess)
+        err = record(ev ? ev->main_end : nullptr, st);
+    if (err != hipSuccess)
+        return err;
+    // events with more tracks than CAP were deferred to the large-team launch
+    if (A.p.max_tracks > CAP) {
+        if (ev)
+            ev->large = true;
+        err = record(ev ? ev->large_begin : nullptr, st);
+        if (err == hipSuccess)
+            err = launch_one<kBigWaves, kBigCapacity, true, DEBUG>(A, 1, 0, st);
+        if (err == hipSuccess)
+            err = record(ev ? ev->large_end : nullptr, st);
+    }
+    return err;
+}
+
+template <bool DEBUG>
+static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
+{
+    switch (s.waves_per_team * 10000 + s.track_capacity) {
+    case 10256: return launch_pair<1, 256, DEBUG>(A, s, st, ev);
+    case 10512: return launch_pair<1, 512, DEBUG>(A, s, st, ev);
+    case 11024: return launch_pair<1, 1024, DEBUG>(A, s, st, ev);
+    case 20256: return launch_pair<2, 256, DEBUG>(A, s, st, ev);
+    case 20512: return launch_pair<2, 512, DEBUG>(A, s, st, ev);
+    case 21024: return launch_pair<2, 1024, DEBUG>(A, s, st, ev);
+    case 40256: return launch_pair<4, 256, DEBUG>(A, s, st, ev);
+    case 40512: return launch_pair<4, 512, DEBUG>(A, s, st, ev);
+    case 41024: return launch_pair<4, 1024, DEBUG>(A, s, st, ev);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev)
+{
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return (int)(debug ? launch_dispatch<true>(args, s, st, ev) : launch_dispatch<false>(args, s, st, ev));
+}
+
+}  // namespace pvk

@@ -1,0 +1,124 @@
+"""libpvfind loads, exports every symbol its header declares, and rejects bad
+arguments on the host (no GPU needed: these calls return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_14966_amd import pvfind as pv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(pv_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 9
+    L = pv.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(pv.pv_params) == 25 * 4
+    assert pv.VERTEX_DTYPE.itemsize == 64 and pv.CLUSTER_DTYPE.itemsize == 32
+    assert ctypes.sizeof(pv.pv_tracks) == 8 * 8
+
+
+def test_defaults_match_paper_constants():
+    p = pv.pv_params_default()
+    vals = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_constants.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                vals[line[0]] = float(line[1])
+    U = 2 ** p.frac_bits
+    assert p.dz == vals["bin_width_mm"]
+    assert p.sigma_max_pp == vals["sigma_max_pp_mm"] and p.sigma_max_gas == vals["sigma_max_gas_mm"]
+    assert p.z_gas == vals["z_gas_boundary_mm"]
+    assert p.min_int_pp == round(vals["min_cluster_integral_pp"] * U)
+    assert p.min_int_gas == round(vals["min_cluster_integral_gas"] * U)
+    assert (p.pv_min_pp, p.pv_min_gas) == (vals["min_tracks_pv_pp"], vals["min_tracks_pv_gas"])
+    assert (p.part_min_pp, p.part_min_gas) == (vals["min_tracks_partition_pp"], vals["min_tracks_partition_gas"])
+    assert p.chi2_max == vals["chi2_max_tukey"] and p.max_iter == vals["max_iterations"]
+    assert p.conv_dchi2 == pytest.approx(vals["conv_dchi2"]) and p.conv_dz == pytest.approx(vals["conv_dz_mm"])
+    assert p.max_rho_pp == pytest.approx(vals["max_rho_pp_mm"])
+    assert pv.pv_nbins(p) == 4000
+
+
+def test_nbins_rejects_fractional_ranges():
+    assert pv.pv_nbins(pv.make_params({"z_max": 400.1})) == -1
+    assert pv.pv_nbins(pv.make_params({"dz": 0.0})) == -1
+    assert pv.pv_nbins(pv.make_params({"z_min": -550.0, "z_max": 300.0})) == 3400
+    assert pv.pv_nbins(pv.make_params({"dz": 0.1})) == -1   # 10000 bins > 4096
+
+
+def _call(params=None, n_events=1, null=None, schedule=None):
+    L = pv.lib()
+    fake = 0x1000   # never dereferenced: every case below fails host validation first
+    tr = pv.pv_tracks(*([fake] * 8))
+    if null == "track":
+        tr.cov_txtx = None
+    bl = pv.pv_beamline(0, 0, 0, 0)
+    ov = pv.pv_vertices_out(fake, fake, fake)
+    ot = pv.pv_track_out(fake, None if null == "out" else fake)
+    p = params or pv.pv_params_default()
+    offs = None if null == "offsets" else ctypes.c_void_p(fake)
+    if schedule is not None:
+        return L.pv_find_sched(ctypes.byref(tr), offs, n_events, ctypes.byref(bl), ctypes.byref(p),
+                               ctypes.byref(ov), ctypes.byref(ot), ctypes.byref(schedule), None)
+    return L.pv_find(ctypes.byref(tr), offs, n_events, ctypes.byref(bl), ctypes.byref(p), ctypes.byref(ov),
+                     ctypes.byref(ot), None)
+
+
+@pytest.mark.parametrize("null", ["track", "out", "offsets"])
+def test_null_pointers_rejected(null):
+    assert _call(null=null) == pv.PV_EINVAL
+    assert pv.pv_last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("frac_bits", 0), ("frac_bits", 19), ("max_vertices_per_event", 0), ("max_vertices_per_event", 129),
+    ("max_tracks_per_event", 4097), ("max_iter", 0), ("chi2_max", 0.0), ("u0", -1.0), ("dip_prom", 0),
+    ("proto_thr", -1), ("z_max", 400.3), ("sigma_max_pp", float("nan")), ("sing_ratio", 1.0),
+])
+def test_bad_params_rejected(field, value):
+    assert _call(params=pv.make_params({field: value})) == pv.PV_EINVAL
+    assert field.split("_")[0] in pv.pv_last_error() or "params" in pv.pv_last_error()
+
+
+def test_negative_event_count_and_bad_schedule_rejected():
+    assert _call(n_events=-1) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(3, 512, 1, 0)) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(1, 300, 1, 0)) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(1, 512, 5, 0)) == pv.PV_EINVAL
+
+
+def test_zero_events_is_a_no_op():
+    assert _call(n_events=0) == pv.PV_OK
+
+
+def test_schedule_round_trip():
+    old = pv.pv_get_schedule()
+    try:
+        pv.pv_set_schedule(2, 1024, 2, 3)
+        s = pv.pv_get_schedule()
+        assert (s.waves_per_team, s.track_capacity, s.persistent, s.teams_per_cu) == (2, 1024, 2, 3)
+        with pytest.raises(pv.PvError):
+            pv.pv_set_schedule(5, 512, 1, 0)
+    finally:
+        pv.lib().pv_set_schedule(ctypes.byref(old))

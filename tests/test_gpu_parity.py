@@ -1,0 +1,204 @@
+"""Parity of the HIP path with the CPU oracle on the GPU (bars in parity.py).
+
+Every call goes through the C ABI (paper_2412_14966_amd.pvfind -> libpvfind).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_14966_amd import pvfind as pv
+from paper_2412_14966_amd import synth
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [dict(waves_per_team=w, track_capacity=c, persistent=m, teams_per_cu=0)
+             for w in (1, 2, 4) for c in (256, 512, 1024) for m in (1, 2)]
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pv.lib()
+    yield
+
+
+def run_both(batch, params=None, schedule=None, debug=True, name=""):
+    p = pv.make_params(params)
+    say(f"{name}: {batch.n_events} events, {batch.n_tracks} tracks, schedule={schedule}, debug={debug}")
+    g = pv.run(batch, params, schedule=schedule, debug=debug)
+    o = oracle.find(batch, parity.oracle_params(p), debug=debug)
+    return g, o
+
+
+def check(batch, params=None, schedule=None, debug=True, name="", max_tie_frac=0.01, fit=True):
+    g, o = run_both(batch, params, schedule, debug, name)
+    rep = parity.compare(batch, g, o, debug=debug, fit=fit)
+    say(f"{name}: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+    assert rep.ties <= max(2, max_tie_frac * rep.n_vertices)
+    return g, o, rep
+
+
+def test_projection_bit_exact_on_a_million_tracks():
+    """Random tracks (slopes down to 1e-3, not from vertices): the binary32
+    projection, the histogram, clusters and association must be bit-exact.
+    Their 'vertices' are fits of unrelated tracks with normal matrices of
+    condition ~1e6, which a binary32 fit does not follow; the fit is compared
+    on the physical workloads below."""
+    rng = np.random.default_rng(20)
+    n = 1 << 20
+    cols = np.zeros((n, 8))
+    cols[:, 0:2] = rng.normal(0, 0.1, (n, 2))
+    cols[:, 2] = rng.uniform(-650, 450, n)
+    cols[:, 3:5] = rng.normal(0, 0.3, (n, 2)) * rng.choice([1e-3, 1e-2, 1.0, 3.0], (n, 1))
+    cols[:, 5] = rng.uniform(1e-5, 3e-3, n)
+    # 1024 events of 1024 tracks
+    b = synth.from_tracks(np.split(cols, 1024), beamline=(0.01, -0.02, 1e-4, -2e-4))
+    check(b, {"max_tracks_per_event": 1024}, name="projection 1M", fit=False)
+
+
+def test_config1_full_parity_debug():
+    b = synth.generate("pp_mu5_100ev")
+    check(b, name="pp mu=5 100 events")
+
+
+def test_config1_tilted_offset_beamline_and_slope_covariance():
+    b = synth.generate("pp_mu5_100ev", beamline=(1.092, 0.472, 2e-4, -1e-4), slope_cov=True)
+    check(b, name="offset tilted beamline, slope covariance")
+
+
+def _exact_event(P, n, rng, slopes=None, var=2.0 ** -11):
+    rows = []
+    for k in range(n):
+        tx, ty = (slopes if slopes is not None else (rng.integers(-40, 41) / 128.0, rng.integers(-40, 41) / 128.0))
+        if tx == 0 and ty == 0:
+            tx = 0.25
+        d = (0.0, 2.0, -1.5)[k % 3]
+        rows.append([P[0] + tx * d, P[1] + ty * d, P[2] + d, tx, ty, var, 0, 0])
+    return np.array(rows)
+
+
+def test_adversarial_events():
+    rng = np.random.default_rng(21)
+    evs = []
+    evs.append(np.zeros((0, 8)))                                            # empty
+    evs.append(np.array([[0.01, 0.02, 3.0, 0.2, 0.1, 1e-3, 0, 0]]))         # one track
+    par = np.zeros((40, 8))                                                 # parallel to the beam
+    par[:, 2] = rng.uniform(-10, 10, 40)
+    par[:, 5] = 1e-3
+    evs.append(par)
+    evs.append(_exact_event((0.0, 0.0, 12.0), 30, rng, slopes=(0.25, 0.0)))  # identical slopes: singular fit
+    wide = np.zeros((60, 8))                                                # wide tracks at the ends
+    wide[:30, 2] = rng.uniform(-600, -590, 30)
+    wide[:30, 3] = rng.choice([0.004, -0.005], 30)
+    wide[:30, 5] = 1e-3
+    wide[30:, 2] = rng.uniform(396, 399.99, 30)
+    wide[30:, 3] = rng.choice([0.03, -0.025], 30)
+    wide[30:, 5] = 1e-3
+    evs.append(wide)
+    bad = _exact_event((0.0, 0.0, -20.0), 25, rng)                          # NaN, Inf, zero/negative variance
+    bad[0, 0] = np.nan
+    bad[1, 4] = np.inf
+    bad[2, 5] = 0.0
+    bad[3, 5] = -1e-3
+    bad[4, 7] = np.nan
+    evs.append(bad)
+    evs.append(_exact_event((0.0, 0.0, 100.0), 25, rng) + 0.0)              # noise-free vertex
+    two = np.concatenate([_exact_event((0.0, 0.0, 30.0), 20, rng), _exact_event((0.0, 0.0, 31.0), 20, rng)])
+    evs.append(two)                                                         # two vertices 1 mm apart
+    b = synth.from_tracks(evs)
+    check(b, name="adversarial")
+
+
+def test_events_larger_than_a_small_team_and_too_many_tracks():
+    big = synth.generate("pp_mu40_20kev", n_events=6, mu=150.0)             # ~3900 tracks each
+    sizes = np.diff(big.offsets)
+    say(f"large events sizes {sizes.tolist()}")
+    b = synth.concat([synth.generate("pp_mu5_100ev", n_events=5), big])
+    check(b, name="large events")
+    lim = int(np.sort(sizes)[2])
+    check(b, {"max_tracks_per_event": lim}, name=f"too many tracks (limit {lim})")
+
+
+def test_vertex_overflow_and_region_parameters():
+    b = synth.generate("pp_mu5_gas_50kev", n_events=60)
+    check(b, {"max_vertices_per_event": 3}, name="overflow, 3 vertex slots")
+    check(b, {"z_min": -550.0, "z_max": 300.0}, name="paper histogram range")
+
+
+def test_invalid_offsets():
+    b = synth.generate("pp_mu5_100ev", n_events=4)
+    n = b.n_tracks
+    o1 = b.offsets.copy()
+    k = int(o1[2])
+    offs = np.array([0, int(o1[1]), -1, k, n], dtype=np.int32)               # events 1, 2 invalid
+    bb = synth.TrackBatch(offsets=offs, **{f: getattr(b, f) for f in synth.TRACK_FIELDS})
+    check(bb, name="invalid offsets")
+    offs = np.array([0, int(o1[1]), n + 5, n], dtype=np.int32)
+    bb = synth.TrackBatch(offsets=offs, **{f: getattr(b, f) for f in synth.TRACK_FIELDS})
+    check(bb, name="offsets beyond the track count")
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: f"w{s['waves_per_team']}c{s['track_capacity']}m{s['persistent']}")
+def test_schedules_agree(sched):
+    b = synth.generate("pp_mu5_100ev", n_events=60)
+    g, o, rep = check(b, schedule=sched, debug=True, name=f"schedule {sched}")
+    g2 = pv.run(b, schedule=sched, debug=True)
+    # same schedule twice: bit-identical, floats included
+    assert np.array_equal(g.track_weight.view(np.uint32), g2.track_weight.view(np.uint32))
+    assert np.array_equal(g.vertices.view(np.uint8), g2.vertices.view(np.uint8))
+    # integer outputs identical to the default schedule
+    g0 = pv.run(b, debug=True)
+    assert np.array_equal(g.track_vertex, g0.track_vertex) and np.array_equal(g.n_vertices, g0.n_vertices)
+    assert np.array_equal(g.hist, g0.hist)
+
+
+def test_track_order_and_batch_composition_invariance():
+    b = synth.generate("pp_mu5_100ev", n_events=40)
+    g = pv.run(b, debug=True)
+    rng = np.random.default_rng(22)
+    perm = np.concatenate([b.offsets[e] + rng.permutation(b.offsets[e + 1] - b.offsets[e])
+                           for e in range(b.n_events)])
+    bs = synth.TrackBatch(offsets=b.offsets.copy(), **{f: getattr(b, f)[perm] for f in synth.TRACK_FIELDS})
+    say("shuffled tracks")
+    gs = pv.run(bs, debug=True)
+    assert np.array_equal(g.hist, gs.hist) and np.array_equal(g.n_vertices, gs.n_vertices)
+    assert np.array_equal(g.track_vertex[perm], gs.track_vertex)
+    assert np.max(np.abs(g.track_weight[perm] - gs.track_weight)) < parity.W_TOL
+    # an event alone equals the same event inside the batch, bit for bit
+    for e in (0, 17, 39):
+        say(f"event {e} alone")
+        ga = pv.run(b.event(e), debug=True)
+        n = int(g.n_vertices[e])
+        assert int(ga.n_vertices[0]) == n
+        assert np.array_equal(ga.vertices[0, :n].view(np.uint8), g.vertices[e, :n].view(np.uint8))
+        a0, a1 = b.offsets[e], b.offsets[e + 1]
+        assert np.array_equal(ga.track_weight.view(np.uint32), g.track_weight[a0:a1].view(np.uint32))
+
+
+def test_config2_full_size_bench_launch():
+    """10,000 events at mu = 5 in the benchmark's launch configuration (default
+    schedule, no debug outputs), every event compared with the oracle."""
+    b = synth.generate("pp_mu5_10kev", keep_truth=False)
+    check(b, debug=False, name="pp mu=5 10k events")
+
+
+def test_config3_beam_gas_sample():
+    b = synth.generate("pp_mu5_gas_50kev", n_events=5000, keep_truth=False)
+    check(b, debug=True, name="pp + beam-gas 5k events")
+
+
+def test_config4_high_pileup_sample():
+    b = synth.generate("pp_mu40_20kev", n_events=800, keep_truth=False)
+    check(b, debug=True, name="mu=40 800 events")

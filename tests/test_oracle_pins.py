@@ -747,3 +747,30 @@ def test_final_selection_beamline_distance_and_regions():
     assert nv((0.35, 0.0, -400.0)) == 1
     # tilted beamline: the distance is measured to the beamline at the vertex z
     assert nv((0.35, 0.0, 100.0), beam=(0.0, 0.0, 0.0035, 0.0)) == 1
+
+
+def test_fit_singular_when_one_track_keeps_weight():
+    """A single weighted track leaves z undetermined: the normal matrix has rank
+    2 and the fit must fail whatever the rounding (det / prod(diag) reading).
+    Two tracks with different slopes determine the vertex; the rule is
+    invariant under a common scaling of the track variances."""
+    P = (0.0, 0.0, 5.0)
+    one = np.array([[P[0], P[1], P[2], 0.25, 0.125, 2.0 ** -11, 0, 0],
+                    [P[0] + 5.0, P[1], P[2], -0.25, 0.0, 2.0 ** -11, 0, 0]])   # second track far outside
+    bad, _, w = oracle.fit(one, P)
+    assert bad and np.all(w == 0)
+    two = np.array([[P[0], P[1], P[2], 0.25, 0.125, 2.0 ** -11, 0, 0],
+                    [P[0], P[1], P[2], -0.25, 0.0, 2.0 ** -11, 0, 0]])
+    bad, v, w = oracle.fit(two, (0.01, 0.0, 5.2))
+    assert not bad and abs(v["z"] - 5.0) < 1e-9
+    for scale in (2.0 ** -20, 2.0 ** 20):
+        s = two.copy()
+        s[:, 5] *= scale
+        assert not oracle.fit(s, (0.0, 0.0, 5.0))[0]
+    # nearly parallel pair: det / prod(diag) = |t1 - t2|^2 / (2 (|t1|^2 + |t2|^2)) here
+    near = two.copy()
+    near[1, 3:5] = [0.25 + 2.0 ** -10, 0.125]
+    ratio = (2.0 ** -10) ** 2 / (2 * (2 * 0.25 ** 2 + 2 * 0.125 ** 2))
+    assert ratio < 1e-4
+    assert oracle.fit(near, (0.0, 0.0, 5.0))[0]
+    assert not oracle.fit(near, (0.0, 0.0, 5.0), {"sing_ratio": ratio / 2})[0]
