@@ -148,6 +148,10 @@ typedef struct {
     int32_t    *n_clusters;            /* n_events: clusters written for the event     */
     float      *zpoca, *sigma;         /* per track, Eq. 1 and Eq. 3                   */
     int32_t    *bin;                   /* per track central bin, -1 outside            */
+    uint32_t   *stage_cycles;          /* n_events * 8 shader-clock cycles spent by the
+                                          event's team in: clear, project+fill, peak
+                                          search, association, gather, fit, selection,
+                                          final weights and outputs                    */
 } pv_debug_out;
 
 /* How a batch is mapped onto the GPU.  Zero fields mean "library choice". */

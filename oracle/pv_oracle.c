@@ -162,11 +162,14 @@ int orc_project(const float trk[8], const float beam[4], const orc_params *p,
  * P(e_{j+1}) - P(e_j), in integer units of 2^-frac_bits track, so every
  * histogrammed track adds exactly 2^frac_bits; the first edge of the
  * histogram counts as P = 0 and the last as P = 1, so mass beyond the range
- * lands in the end bins.
+ * lands in the end bins.  In binary32 the division by u0 sigma is a product
+ * with its rounded reciprocal, taken once per track: s = (e - z_poca) r with
+ * r = 1 / (u0 sigma).
  */
 int orc_edge_code(float e, float zp, float sw, int frac_bits)
 {
-    float s = div32(sub32(e, zp), sw);
+    const float r = div32(1.0f, sw);
+    float s = mul32(sub32(e, zp), r);
     if (s < -1.0f)
         s = -1.0f;
     if (s > 1.0f)

@@ -90,7 +90,8 @@ int  orc_project(const float trk[8], const float beam[4], const orc_params *p,
                  float *zpoca, float *sigma, int *bin);
 
 /* fixed-point cumulative kernel mass left of edge e for a track at zp with
-   half-width sw (Sec. 3.2, cubic approximation of the Gaussian CDF) */
+   half-width sw (Sec. 3.2, cubic approximation of the Gaussian CDF);
+   s = (e - zp) * fl(1 / sw) in binary32 */
 int  orc_edge_code(float e, float zp, float sw, int frac_bits);
 
 /* histogram and per-bin associable-track counts of one event */

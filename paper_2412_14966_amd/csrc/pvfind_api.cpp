@@ -139,6 +139,7 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
     k.z_min = p->z_min;
     k.z_max = p->z_max;
     k.dz = p->dz;
+    k.inv_dz = 1.0f / p->dz;
     k.u0 = p->u0;
     k.sigma_max_pp = p->sigma_max_pp;
     k.sigma_max_gas = p->sigma_max_gas;
@@ -258,6 +259,7 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         A.dbg_zp = dbg->zpoca;
         A.dbg_sg = dbg->sigma;
         A.dbg_bin = dbg->bin;
+        A.dbg_cycles = dbg->stage_cycles;
     }
     bool timing;
     {

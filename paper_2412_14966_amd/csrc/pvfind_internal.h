@@ -20,7 +20,7 @@ constexpr int kTrNonfinite = 4;
 
 // Parameters as the kernels use them, derived once on the host.
 struct KParams {
-    float z_min, z_max, dz, u0;
+    float z_min, z_max, dz, u0, inv_dz;
     float sigma_max_pp, sigma_max_gas;
     float unit;                 // 2^frac_bits
     int nb, gas_bin;
@@ -59,6 +59,7 @@ struct KArgs {
     int32_t *dbg_ncl;
     float *dbg_zp, *dbg_sg;
     int32_t *dbg_bin;
+    uint32_t *dbg_cycles;
     WorkQueue *wq;
     KParams p;
 };

@@ -97,11 +97,44 @@ __device__ __forceinline__ int wave_min(int v)
     return v;
 }
 
-__device__ __forceinline__ float group_sum(float v, int L)
+// Sum over aligned groups of L lanes; every lane of a group gets the same
+// bits (the pairs added are the same, addition is commutative).  Within a
+// row of 16 lanes the partners come from DPP (quad permutes, half-row and
+// row mirrors), across rows from a swizzle and a permute.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
 {
-    for (int off = 1; off < L; off <<= 1)
-        v += __shfl_xor(v, off);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+template <int L>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if (L >= 2)
+        v += dpp_f<0xB1>(v);     // quad_perm [1,0,3,2]
+    if (L >= 4)
+        v += dpp_f<0x4E>(v);     // quad_perm [2,3,0,1]
+    if (L >= 8)
+        v += dpp_f<0x141>(v);    // row_half_mirror: lane i <-> 7 - i
+    if (L >= 16)
+        v += dpp_f<0x140>(v);    // row_mirror: lane i <-> 15 - i
+    if (L >= 32)
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));   // xor 16
+    if (L >= 64)
+        v += __shfl_xor(v, 32);
     return v;
+}
+
+__device__ __forceinline__ void load_track(const KArgs &A, int g, float t[8])
+{
+    t[0] = A.x[g];
+    t[1] = A.y[g];
+    t[2] = A.z[g];
+    t[3] = A.tx[g];
+    t[4] = A.ty[g];
+    t[5] = A.cxx[g];
+    t[6] = A.cxtx[g];
+    t[7] = A.ctxtx[g];
 }
 
 // ---------------------------------------------------------------------------
@@ -150,9 +183,10 @@ __device__ __forceinline__ Proj project(float x, float y, float z, float tx, flo
 // ---------------------------------------------------------------------------
 // Sec. 3.2: kernel mass left of a bin edge, cubic cumulative, fixed point
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int edge_code(float e, float zp, float sw, float unit)
+// r = 1 / (u0 sigma), correctly rounded, once per track
+__device__ __forceinline__ int edge_code(float e, float zp, float r, float unit)
 {
-    float s = (e - zp) / sw;
+    float s = (e - zp) * r;
     if (s < -1.0f)
         s = -1.0f;
     if (s > 1.0f)
@@ -161,34 +195,103 @@ __device__ __forceinline__ int edge_code(float e, float zp, float sw, float unit
     return (int)rintf(P * unit);
 }
 
-__device__ __forceinline__ void fill_track(int *hist, unsigned long long *occ, float zp, float sw,
-                                           const KParams &p)
+// Window of edges [jl, jh] whose codes are computed for a track at zp with
+// half-width sw: any superset of the kernel's support gives the same
+// integers, so the bounds may be approximate; one extra edge on each side
+// makes the end codes exactly 0 and 'full'.
+struct Window {
+    int jl, jh;   // bins jl .. jh-1 receive mass
+};
+
+__device__ __forceinline__ Window track_window(float zp, float sw, const KParams &p)
 {
-    // any superset of the kernel's support gives the same integers
-    const float fl = fmaxf(floorf((zp - sw - p.z_min) / p.dz) - 1.0f, 0.0f);
-    const float fh = fminf(ceilf((zp + sw - p.z_min) / p.dz) + 1.0f, (float)p.nb);
-    const int jl = (int)fl, jh = (int)fh;
-    if (jh <= jl)
-        return;
-    const int full = (int)p.unit;
-    int prev = (jl == 0) ? 0 : edge_code(p.z_min + (float)jl * p.dz, zp, sw, p.unit);
-    for (int j = jl; j < jh; ++j) {
-        const int next = (j + 1 == p.nb) ? full : edge_code(p.z_min + (float)(j + 1) * p.dz, zp, sw, p.unit);
-        const int d = next - prev;
-        if (d != 0)
-            atomicAdd(&hist[j], d);
-        prev = next;
+    const float fl = fmaxf(floorf((zp - sw - p.z_min) * p.inv_dz) - 1.0f, 0.0f);
+    const float fh = fminf(ceilf((zp + sw - p.z_min) * p.inv_dz) + 1.0f, (float)p.nb);
+    return Window{(int)fl, (int)fh};
+}
+
+__device__ __forceinline__ int code_at(int j, float zp, float r, const KParams &p)
+{
+    // first edge of the histogram: P = 0; last edge: P = 1
+    if (j <= 0)
+        return 0;
+    if (j >= p.nb)
+        return (int)p.unit;
+    return edge_code(p.z_min + (float)j * p.dz, zp, r, p.unit);
+}
+
+constexpr int kShortWindow = 8;   // bins per lane in the per-lane pass
+
+// per-lane pass: windows of at most kShortWindow bins, fixed trip count
+__device__ __forceinline__ void fill_short(int *hist, Window w, float zp, float r, const KParams &p)
+{
+    int prev = code_at(w.jl, zp, r, p);
+#pragma unroll
+    for (int u = 0; u < kShortWindow; ++u) {
+        const int j = w.jl + u;
+        if (j < w.jh) {
+            const int next = code_at(j + 1, zp, r, p);
+            const int d = next - prev;
+            if (d != 0)
+                atomicAdd(&hist[j], d);
+            prev = next;
+        }
     }
-    const int wl = jl >> 6, wh = (jh - 1) >> 6;
-    atomicOr(occ, (2ull << wh) - (1ull << wl));
+}
+
+__device__ __forceinline__ unsigned long long window_words(Window w)
+{
+    const int wl = w.jl >> 6, wh = (w.jh - 1) >> 6;
+    return (2ull << wh) - (1ull << wl);
 }
 
 // ---------------------------------------------------------------------------
 // Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e].
 // Returns the number of clusters; with `write` stores them from index `first`.
 // ---------------------------------------------------------------------------
+// Bins [s, e] are read 8 at a time with independent LDS loads so that one
+// lane's serial walk pays the LDS latency once per 8 bins.
+__device__ __forceinline__ int sum_bins(const int *h, int s, int e)
+{
+    int tot = 0;
+    for (int k0 = s; k0 <= e; k0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = (k0 + u <= e) ? h[k0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            tot += v[u];
+    }
+    return tot;
+}
+
+// first index of the highest bin in [s, e]
+__device__ __forceinline__ int argmax_bins(const int *h, int s, int e)
+{
+    int im = s, best = INT_MIN;
+    for (int k0 = s; k0 <= e; k0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = (k0 + u <= e) ? h[k0 + u] : INT_MIN;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (v[u] > best) {
+                best = v[u];
+                im = k0 + u;
+            }
+    }
+    return im;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e]
+// with bin total `tot`.  Returns the number of clusters; with `write` stores
+// them from index `first`.
+// ---------------------------------------------------------------------------
 template <int W, int CAP>
-__device__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, bool write, int first)
+__device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, int tot, bool write, int first)
 {
     const int *h = S.u.hist;
     const bool strad = (s < p.gas_bin) && (e >= p.gas_bin);
@@ -196,15 +299,8 @@ __device__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, bool 
     auto thr = [&](int lo, int hi) -> int {
         if (!strad)
             return ifix;
-        int im = lo;
-        for (int k = lo + 1; k <= hi; ++k)
-            if (h[k] > h[im])
-                im = k;
-        return (im < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
+        return (argmax_bins(h, lo, hi) < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
     };
-    int tot = 0;
-    for (int k = s; k <= e; ++k)
-        tot += h[k];
     int count = 0;
     auto emit = [&](int lo, int hi) {
         if (write) {
@@ -217,32 +313,44 @@ __device__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, bool 
         ++count;
     };
     int cs = s, pcs = 0;
-    int up = 1, M = h[s], m = 0, mj = s, pm = 0, pref = h[s];
-    for (int k = s + 1; k <= e; ++k) {
-        const int hk = h[k];
-        pref += hk;
-        if (up) {
-            if (hk > M) {
+    int up = 1, M = 0, m = 0, mj = s, pm = 0, pref = 0;
+    for (int k0 = s; k0 <= e; k0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = (k0 + u <= e) ? h[k0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            if (k > e)
+                break;
+            const int hk = v[u];
+            pref += hk;
+            if (k == s) {
                 M = hk;
-            } else if (hk <= M - p.dip_prom) {
-                up = 0;
-                m = hk;
-                mj = k;
-                pm = pref;
-            }
-        } else {
-            if (hk < m) {
-                m = hk;
-                mj = k;
-                pm = pref;
-            } else if (hk >= m + p.dip_prom) {
-                if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
-                    emit(cs, mj);
-                    cs = mj + 1;
-                    pcs = pm;
+            } else if (up) {
+                if (hk > M) {
+                    M = hk;
+                } else if (hk <= M - p.dip_prom) {
+                    up = 0;
+                    m = hk;
+                    mj = k;
+                    pm = pref;
                 }
-                up = 1;
-                M = hk;
+            } else {
+                if (hk < m) {
+                    m = hk;
+                    mj = k;
+                    pm = pref;
+                } else if (hk >= m + p.dip_prom) {
+                    if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
+                        emit(cs, mj);
+                        cs = mj + 1;
+                        pcs = pm;
+                    }
+                    up = 1;
+                    M = hk;
+                }
             }
         }
     }
@@ -251,92 +359,93 @@ __device__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, bool 
     return count;
 }
 
-// Whole peak search, run by wavefront 0.
+// Whole peak search, run by wavefront 0.  Proto-cluster runs come from
+// ballots of (bin > proto_thr) over the touched 64-bin words; they are queued
+// and walked 32-64 at a time, one lane per proto-cluster.
 template <int W, int CAP>
-__device__ void peak_search(Smem<W, CAP> &S, const KParams &p)
+__device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
 {
     const int lane = threadIdx.x & 63;
     int n_found = 0, npend = 0, open_s = -1, prev_w = -2;
-
-    auto flush = [&]() {
-        const bool has = lane < npend;
-        int s = 0, e = 0;
-        if (has) {
-            s = S.ps[lane];
-            e = S.pe[lane];
-        }
-        const int c = has ? walk_proto(S, p, s, e, false, 0) : 0;
-        const int incl = wave_incl_scan(c, lane);
-        if (has)
-            walk_proto(S, p, s, e, true, n_found + incl - c);
-        n_found += __shfl(incl, 63);
-        npend = 0;
-        __builtin_amdgcn_wave_barrier();
-    };
-    auto push = [&](int s, int e) {
+    unsigned long long occ = S.occ;
+    auto push = [&](int s, int e) __attribute__((always_inline)) {
         if (lane == 0) {
             S.ps[npend] = (short)s;
             S.pe[npend] = (short)e;
         }
-        __builtin_amdgcn_wave_barrier();
         ++npend;
-        if (npend == 64)
-            flush();
     };
-
-    unsigned long long occ = S.occ;
-    while (occ) {
-        const int w = __ffsll((long long)occ) - 1;
-        occ &= occ - 1ull;
-        if (open_s >= 0 && prev_w != w - 1) {
+    for (;;) {
+        const bool last = (occ == 0ull);
+        if (!last) {
+            // one word adds at most 32 runs plus the close of an open one
+            const int w = __ffsll((long long)occ) - 1;
+            occ &= occ - 1ull;
+            if (open_s >= 0 && prev_w != w - 1) {
+                push(open_s, 64 * prev_w + 63);
+                open_s = -1;
+            }
+            const int j = 64 * w + lane;
+            const int hv = (j < p.nb) ? S.u.hist[j] : 0;
+            const unsigned long long m = __ballot(hv > p.proto_thr);
+            unsigned long long st = m & ~(m << 1);
+            unsigned long long en = m & ~(m >> 1);
+            int cur = -1;
+            if (open_s >= 0) {
+                if (m & 1ull) {
+                    cur = open_s;
+                    st &= ~1ull;
+                } else {
+                    push(open_s, 64 * w - 1);
+                }
+                open_s = -1;
+            }
+            while (en) {
+                const int eb = __ffsll((long long)en) - 1;
+                en &= en - 1ull;
+                if (cur < 0) {
+                    const int sb = __ffsll((long long)st) - 1;
+                    st &= st - 1ull;
+                    cur = 64 * w + sb;
+                }
+                if (eb == 63)
+                    open_s = cur;
+                else
+                    push(cur, 64 * w + eb);
+                cur = -1;
+            }
+            prev_w = w;
+        } else if (open_s >= 0) {
             push(open_s, 64 * prev_w + 63);
             open_s = -1;
         }
-        const int j = 64 * w + lane;
-        const int hv = (j < p.nb) ? S.u.hist[j] : 0;
-        const unsigned long long m = __ballot(hv > p.proto_thr);
-        unsigned long long st = m & ~(m << 1);
-        unsigned long long en = m & ~(m >> 1);
-        int cur = -1;
-        if (open_s >= 0) {
-            if (m & 1ull) {
-                cur = open_s;
-                st &= ~1ull;
-            } else {
-                push(open_s, 64 * w - 1);
+        __builtin_amdgcn_wave_barrier();
+        if (npend >= 32 || (last && npend > 0)) {
+            const bool has = lane < npend;
+            int s = 0, e = 0;
+            if (has) {
+                s = S.ps[lane];
+                e = S.pe[lane];
             }
-            open_s = -1;
+            const int tot = has ? sum_bins(S.u.hist, s, e) : 0;
+            const int c = has ? walk_proto(S, p, s, e, tot, false, 0) : 0;
+            const int incl = wave_incl_scan(c, lane);
+            if (has)
+                walk_proto(S, p, s, e, tot, true, n_found + incl - c);
+            n_found += __shfl(incl, 63);
+            npend = 0;
+            __builtin_amdgcn_wave_barrier();
         }
-        while (en) {
-            const int eb = __ffsll((long long)en) - 1;
-            en &= en - 1ull;
-            if (cur < 0) {
-                const int sb = __ffsll((long long)st) - 1;
-                st &= st - 1ull;
-                cur = 64 * w + sb;
-            }
-            if (eb == 63)
-                open_s = cur;
-            else
-                push(cur, 64 * w + eb);
-            cur = -1;
-        }
-        prev_w = w;
+        if (last)
+            break;
     }
-    if (open_s >= 0)
-        push(open_s, 64 * prev_w + 63);
-    if (npend > 0)
-        flush();
 
     const int ncl = min(n_found, p.max_vertices);
     // seeds (Eq. 4-5): first highest bin, parabola-like correction from the neighbours
     for (int q = lane; q < ncl; q += 64) {
         const int lo = S.clo[q], hi = S.chi[q];
         const int *h = S.u.hist;
-        int im = lo;
-        for (int k = lo + 1; k <= hi; ++k)
-            if (h[k] > h[im])
-                im = k;
+        const int im = argmax_bins(h, lo, hi);
         const int Ni = h[im];
         const int Nm = (im > 0) ? h[im - 1] : 0;
         const int Np = (im + 1 < p.nb) ? h[im + 1] : 0;
@@ -390,10 +499,226 @@ __device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
 }
 
 // ---------------------------------------------------------------------------
+// Sec. 3.5: Newton-Raphson fit of every live vertex, L lanes per vertex.
+// Each lane keeps up to kRegTracks of its vertex's tracks in registers for
+// all iterations (the rest, if any, is re-read from LDS each iteration).
+// ---------------------------------------------------------------------------
+constexpr int kRegTracks = 8;
+
+struct FitSums {
+    float s0, sx, sy, szz, gx, gy, gz, sw;
+};
+
+__device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float tx, float ty, float wt, float dx,
+                                           float dy, float dz, const KParams &p)
+{
+    // residual (Eq. 9) relative to the frame origin, chi2 (Eq. 7), Tukey weight (Eq. 17)
+    const float rx = fmaf(dz, tx, X) - dx;
+    const float ry = fmaf(dz, ty, Y) - dy;
+    const float chi2 = wt * fmaf(rx, rx, ry * ry);
+    if (chi2 < p.chi2_max) {
+        const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
+        const float w = u * u;
+        const float ww = w * wt;
+        a.sw += w;
+        a.s0 += ww;
+        a.sx = fmaf(ww, tx, a.sx);
+        a.sy = fmaf(ww, ty, a.sy);
+        a.szz = fmaf(ww, fmaf(tx, tx, ty * ty), a.szz);
+        const float px = ww * rx, py = ww * ry;
+        a.gx += px;
+        a.gy += py;
+        a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
+    }
+}
+
+template <int W, int CAP, int L>
+__device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, int nl)
+{
+    constexpr int NT = 64 * W;
+    constexpr int G = NT / L;
+    const int tid = threadIdx.x;
+    const int gid = tid / L, gl = tid % L;
+    for (int k0 = 0; k0 < nl; k0 += G) {
+        const int k = k0 + gid;
+        const bool has = k < nl;
+        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+        float rX[kRegTracks], rY[kRegTracks], rTX[kRegTracks], rTY[kRegTracks], rW[kRegTracks];
+#pragma unroll
+        for (int u = 0; u < kRegTracks; ++u) {
+            const int t = gl + u * L;
+            if (t < ck) {
+                const int sl = beg + t;
+                rX[u] = S.u.f.X[sl];
+                rY[u] = S.u.f.Y[sl];
+                rTX[u] = S.u.f.TX[sl];
+                rTY[u] = S.u.f.TY[sl];
+                rW[u] = S.u.f.WT[sl];
+            } else {
+                rX[u] = rY[u] = rTX[u] = rTY[u] = rW[u] = 0.0f;
+            }
+        }
+        // start at the seed: on the beamline, delta dz above the bin centre
+        const float d0 = has ? S.cd0[S.live[k]] : 0.0f;
+        float dx = p.btx * d0, dy = p.bty * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f, ld = 0.0f;
+        int nit = 0;
+        bool active = has, failed = false, conv = false;
+        for (int it = 1; it <= p.max_iter; ++it) {
+            if (!__any(active))
+                break;
+            FitSums a = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < kRegTracks; ++u)
+                    if (rW[u] > 0.0f)
+                        accumulate(a, rX[u], rY[u], rTX[u], rTY[u], rW[u], dx, dy, dz, p);
+                for (int t = gl + kRegTracks * L; t < ck; t += L) {
+                    const int sl = beg + t;
+                    const float wt = S.u.f.WT[sl];
+                    if (wt > 0.0f)
+                        accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
+                }
+            }
+            const float s0 = group_sum<L>(a.s0), sx = group_sum<L>(a.sx), sy = group_sum<L>(a.sy);
+            const float szz = group_sum<L>(a.szz), gx = group_sum<L>(a.gx), gy = group_sum<L>(a.gy);
+            const float gz = group_sum<L>(a.gz), sw = group_sum<L>(a.sw);
+            if (active) {
+                // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
+                // det(A) = s0 * D, singular when det <= sing_ratio * s0 * s0 * szz
+                const float D = fmaf(s0, szz, -fmaf(sx, sx, sy * sy));
+                if (!(sw > 0.0f) || !(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
+                    failed = true;
+                    active = false;
+                } else {
+                    // eliminate x and y: D dz = sx gx + sy gy - s0 gz, then s0 dx = gx + sx dz
+                    const float rs0 = __builtin_amdgcn_rcpf(s0);
+                    const float ddz = fmaf(sx, gx, fmaf(sy, gy, -s0 * gz)) * __builtin_amdgcn_rcpf(D);
+                    const float ddx = fmaf(sx, ddz, gx) * rs0;
+                    const float ddy = fmaf(sy, ddz, gy) * rs0;
+                    const float dchi2 = fmaf(ddz, gz, -fmaf(ddx, gx, ddy * gy));   // Eq. 16
+                    dx += ddx;
+                    dy += ddy;
+                    dz += ddz;
+                    la = s0;
+                    lb = sx;
+                    lc = sy;
+                    ld = szz;
+                    nit = it;
+                    if (fabsf(dchi2) < p.conv_dchi2 && fabsf(ddz) < p.conv_dz) {
+                        conv = true;
+                        active = false;
+                    }
+                }
+            }
+        }
+        if (has && gl == 0) {
+            S.vdx[k] = dx;
+            S.vdy[k] = dy;
+            S.vdz[k] = dz;
+            S.va[k] = la;
+            S.vb[k] = lb;
+            S.vc[k] = lc;
+            S.vd[k] = ld;
+            S.vinfo[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
+        }
+    }
+}
+
+// Final Tukey weights at the fitted position, per-track outputs, chi2 and
+// ndof (2 sum w - 3), covariance (Eq. 14) and the vertex record.
+template <int W, int CAP, int L>
+__device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int e, int a, int nl)
+{
+    constexpr int NT = 64 * W;
+    constexpr int G = NT / L;
+    const KParams &p = A.p;
+    const int tid = threadIdx.x;
+    const int gid = tid / L, gl = tid % L;
+    for (int k0 = 0; k0 < nl; k0 += G) {
+        const int k = k0 + gid;
+        const bool has = k < nl;
+        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+        const int vo = has ? S.vout[k] : -1;
+        const float dx = has ? S.vdx[k] : 0.0f, dy = has ? S.vdy[k] : 0.0f, dz = has ? S.vdz[k] : 0.0f;
+        float schi = 0.0f, sw = 0.0f;
+        for (int t = gl; t < ck; t += L) {
+            const int sl = beg + t;
+            const float wt = S.u.f.WT[sl];
+            float w = 0.0f, chi2 = 0.0f;
+            if (wt > 0.0f) {
+                const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
+                const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
+                chi2 = wt * fmaf(rx, rx, ry * ry);
+                if (chi2 < p.chi2_max) {
+                    const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
+                    w = u * u;
+                }
+            }
+            schi = fmaf(w, chi2, schi);
+            sw += w;
+            const int g = a + S.u.f.IDX[sl];
+            A.trk_vtx[g] = vo;
+            A.trk_w[g] = (vo >= 0) ? w : 0.0f;
+        }
+        schi = group_sum<L>(schi);
+        sw = group_sum<L>(sw);
+        if (has && gl == 0 && vo >= 0) {
+            const int cq = S.live[k];
+            const float zr = bin_centre(S.cpk[cq], p);
+            const float la = S.va[k], lb = S.vb[k], lc = S.vc[k], ld = S.vd[k];
+            float cf[6];
+            const float det = inverse_a<float>(la, lb, lc, ld, cf);
+            // 1-norm condition number of A
+            const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
+            const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
+                                         fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
+                                   fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
+            int flags = (S.vinfo[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
+            if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
+                double cd[6];
+                inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
+                for (int q = 0; q < 6; ++q)
+                    cf[q] = (float)cd[q];
+                flags |= PV_VX_FP64_INVERSION;
+            }
+            pv_vertex v;
+            v.x = (p.bx + p.btx * zr) + dx;
+            v.y = (p.by + p.bty * zr) + dy;
+            v.z = zr + dz;
+            for (int q = 0; q < 6; ++q)
+                v.cov[q] = cf[q];
+            v.chi2 = schi;
+            v.ndof = 2.0f * sw - 3.0f;
+            v.z_seed = zr + S.cd0[cq];
+            v.n_tracks = S.cnt[k];
+            v.bin_lo = S.clo[cq];
+            v.bin_hi = S.chi[cq];
+            v.peak_bin = S.cpk[cq];
+            v.n_iter = (uint8_t)(S.vinfo[k] & 0xFF);
+            v.flags = (uint8_t)flags;
+            v.reserved = 0;
+            A.vout[(size_t)e * p.max_vertices + vo] = v;
+        }
+    }
+}
+
+// Stage boundaries for the per-stage cycle counters of the debug variant.
+struct Stamps {
+    unsigned long long t[9];
+};
+
+template <bool DEBUG>
+__device__ __forceinline__ void stamp(Stamps &st, int k)
+{
+    if (DEBUG)
+        st.t[k] = clock64();
+}
+
+// ---------------------------------------------------------------------------
 // one event
 // ---------------------------------------------------------------------------
 template <int W, int CAP, bool BIG, bool DEBUG>
-__device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
+__device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
 {
     constexpr int NT = 64 * W;
     const KParams &p = A.p;
@@ -430,6 +755,8 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
         return;
     }
 
+    Stamps ts;
+    stamp<DEBUG>(ts, 0);
     // clear
     {
         int4 *h4 = reinterpret_cast<int4 *>(S.u.hist);
@@ -443,34 +770,90 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
         }
     }
     __syncthreads();
+    stamp<DEBUG>(ts, 1);
 
-    // project + fill
-    for (int i = tid; i < n; i += NT) {
-        const int g = a + i;
-        const Proj r = project(A.x[g], A.y[g], A.z[g], A.tx[g], A.ty[g], A.cxx[g], A.cxtx[g], A.ctxtx[g], p);
-        if (r.fl & kTrNonfinite)
-            atomicOr(&S.status, PV_EV_NONFINITE_INPUT);
-        if (r.fl & kTrHist)
-            fill_track(S.u.hist, &S.occ, r.zp, p.u0 * r.sg, p);
-        S.tb[i] = (r.bin + 1) | (r.fl << 13);
-        if (DEBUG) {
-            if (A.dbg_zp)
-                A.dbg_zp[g] = r.zp;
-            if (A.dbg_sg)
-                A.dbg_sg[g] = r.sg;
-            if (A.dbg_bin)
-                A.dbg_bin[g] = r.bin;
+    // project + fill.  All lanes run every chunk (wavefront-wide steps below);
+    // the loads of the next chunk are issued before this chunk is filled.
+    // Kernel windows of up to kShortWindow bins are filled by their own lane;
+    // wider ones (about 5 % of tracks at mu = 5) by the whole wavefront, one
+    // track at a time, so no lane idles through another lane's long window.
+    {
+        float cur[8], nxt[8];
+        unsigned long long words = 0ull;
+        if (tid < n)
+            load_track(A, a + tid, cur);
+        for (int i0 = 0; i0 < n; i0 += NT) {
+            const int i = i0 + tid;
+            const bool valid = i < n;
+            if (i + NT < n)
+                load_track(A, a + i + NT, nxt);
+            Proj r{0.0f, 0.0f, -1, 0};
+            if (valid)
+                r = project(cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], cur[6], cur[7], p);
+            bool wide = false;
+            float rinv = 0.0f;
+            Window w{0, 0};
+            if (r.fl & kTrHist) {
+                const float sw = p.u0 * r.sg;
+                rinv = 1.0f / sw;
+                w = track_window(r.zp, sw, p);
+                if (w.jh > w.jl) {
+                    words |= window_words(w);
+                    wide = (w.jh - w.jl) > kShortWindow;
+                    if (!wide)
+                        fill_short(S.u.hist, w, r.zp, rinv, p);
+                }
+            }
+            unsigned long long wm = __ballot(wide);
+            while (wm) {
+                const int src = __ffsll((long long)wm) - 1;
+                wm &= wm - 1ull;
+                const float zs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.zp), src));
+                const float rs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rinv), src));
+                const int jl = __builtin_amdgcn_readlane(w.jl, src);
+                const int jh = __builtin_amdgcn_readlane(w.jh, src);
+                for (int j = jl + lane; j < jh; j += 64) {
+                    const int d = code_at(j + 1, zs, rs, p) - code_at(j, zs, rs, p);
+                    if (d != 0)
+                        atomicAdd(&S.u.hist[j], d);
+                }
+            }
+            if (valid) {
+                if (r.fl & kTrNonfinite)
+                    atomicOr(&S.status, PV_EV_NONFINITE_INPUT);
+                S.tb[i] = (r.bin + 1) | (r.fl << 13);
+                if (DEBUG) {
+                    const int g = a + i;
+                    if (A.dbg_zp)
+                        A.dbg_zp[g] = r.zp;
+                    if (A.dbg_sg)
+                        A.dbg_sg[g] = r.sg;
+                    if (A.dbg_bin)
+                        A.dbg_bin[g] = r.bin;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                cur[q] = nxt[q];
         }
+        // one OR per wavefront into the touched-word mask
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            words |= (unsigned long long)__shfl_xor((long long)words, off);
+        if (lane == 0 && words)
+            atomicOr(&S.occ, words);
     }
     __syncthreads();
     if (DEBUG && A.dbg_hist)
         for (int j = tid; j < p.nb; j += NT)
             A.dbg_hist[(size_t)e * p.nb + j] = S.u.hist[j];
 
+    stamp<DEBUG>(ts, 2);
     // peaks and seeds
     if (wave == 0)
         peak_search(S, p);
     __syncthreads();
+    stamp<DEBUG>(ts, 3);
 
     // association with iterative removal (Sec. 3.4)
     if (wave == 0) {
@@ -535,6 +918,7 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
             break;
     }
     const int nl = S.n_live;
+    stamp<DEBUG>(ts, 4);
 
     if (DEBUG && A.dbg_cl && wave == 0) {
         for (int q = lane; q < S.n_cl; q += 64)
@@ -601,6 +985,9 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
         const int i = c0 + lane;
         const bool valid = i < r1;
         const int own = valid ? (S.tb[i] >> 16) - 1 : -1;
+        float t[8];
+        if (own >= 0)
+            load_track(A, a + i, t);
         unsigned long long rem = __ballot(own >= 0);
         int slot = -1;
         while (rem) {
@@ -618,8 +1005,8 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
         if (valid) {
             const int g = a + i;
             if (slot >= 0) {
-                const float x = A.x[g], y = A.y[g], z = A.z[g], tx = A.tx[g], ty = A.ty[g];
-                const float vxx = A.cxx[g], vxtx = A.cxtx[g], vtxtx = A.ctxtx[g];
+                const float x = t[0], y = t[1], z = t[2], tx = t[3], ty = t[4];
+                const float vxx = t[5], vxtx = t[6], vtxtx = t[7];
                 // positions relative to the beamline point at the peak-bin centre
                 const int cq = S.live[own];
                 const float zr = bin_centre(S.cpk[cq], p);
@@ -640,102 +1027,27 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
         }
     }
     __syncthreads();
+    stamp<DEBUG>(ts, 5);
 
-    // fit (Sec. 3.5): L lanes per vertex
+    // fit (Sec. 3.5): L lanes per vertex, L the largest power of two with
+    // L * vertices <= lanes of the team
     int L = 64;
     {
         const int target = NT / max(nl, 1);
         while (L > 1 && L > target)
             L >>= 1;
     }
-    const int G = NT / L;
-    const int gid = tid / L, gl = tid & (L - 1);
-    for (int k0 = 0; k0 < nl; k0 += G) {
-        const int k = k0 + gid;
-        const bool has = k < nl;
-        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
-        // start at the seed: on the beamline, delta dz above the bin centre
-        const float d0 = has ? S.cd0[S.live[k]] : 0.0f;
-        float dx = p.btx * d0, dy = p.bty * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f, ld = 0.0f;
-        int nit = 0;
-        bool active = has, failed = false, conv = false;
-        for (int it = 1; it <= p.max_iter; ++it) {
-            if (!__any(active))
-                break;
-            float s0 = 0.0f, sx = 0.0f, sy = 0.0f, szz = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f, sw = 0.0f;
-            if (active) {
-                for (int t = gl; t < ck; t += L) {
-                    const int sl = beg + t;
-                    const float wt = S.u.f.WT[sl];
-                    if (!(wt > 0.0f))
-                        continue;
-                    const float tx = S.u.f.TX[sl], ty = S.u.f.TY[sl];
-                    const float rx = fmaf(dz, tx, S.u.f.X[sl]) - dx;
-                    const float ry = fmaf(dz, ty, S.u.f.Y[sl]) - dy;
-                    const float chi2 = wt * fmaf(rx, rx, ry * ry);
-                    if (chi2 < p.chi2_max) {
-                        const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
-                        const float w = u * u;
-                        const float ww = w * wt;
-                        sw += w;
-                        s0 += ww;
-                        sx = fmaf(ww, tx, sx);
-                        sy = fmaf(ww, ty, sy);
-                        szz = fmaf(ww, fmaf(tx, tx, ty * ty), szz);
-                        const float px = ww * rx, py = ww * ry;
-                        gx += px;
-                        gy += py;
-                        gz = fmaf(px, tx, fmaf(py, ty, gz));
-                    }
-                }
-            }
-            s0 = group_sum(s0, L);
-            sx = group_sum(sx, L);
-            sy = group_sum(sy, L);
-            szz = group_sum(szz, L);
-            gx = group_sum(gx, L);
-            gy = group_sum(gy, L);
-            gz = group_sum(gz, L);
-            sw = group_sum(sw, L);
-            if (active) {
-                // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz)
-                // det(A) = s0 * D; singular when det <= sing_ratio * s0 * s0 * szz
-                const float D = fmaf(s0, szz, -fmaf(sx, sx, sy * sy));
-                if (!(sw > 0.0f) || !(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
-                    failed = true;
-                    active = false;
-                } else {
-                    const float ddz = fmaf(sx, gx, fmaf(sy, gy, -s0 * gz)) / D;
-                    const float ddx = fmaf(sx, ddz, gx) / s0;
-                    const float ddy = fmaf(sy, ddz, gy) / s0;
-                    const float dchi2 = fmaf(ddz, gz, -fmaf(ddx, gx, ddy * gy));
-                    dx += ddx;
-                    dy += ddy;
-                    dz += ddz;
-                    la = s0;
-                    lb = sx;
-                    lc = sy;
-                    ld = szz;
-                    nit = it;
-                    if (fabsf(dchi2) < p.conv_dchi2 && fabsf(ddz) < p.conv_dz) {
-                        conv = true;
-                        active = false;
-                    }
-                }
-            }
-        }
-        if (has && gl == 0) {
-            S.vdx[k] = dx;
-            S.vdy[k] = dy;
-            S.vdz[k] = dz;
-            S.va[k] = la;
-            S.vb[k] = lb;
-            S.vc[k] = lc;
-            S.vd[k] = ld;
-            S.vinfo[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
-        }
+    switch (L) {
+    case 1: fit_vertices<W, CAP, 1>(S, p, nl); break;
+    case 2: fit_vertices<W, CAP, 2>(S, p, nl); break;
+    case 4: fit_vertices<W, CAP, 4>(S, p, nl); break;
+    case 8: fit_vertices<W, CAP, 8>(S, p, nl); break;
+    case 16: fit_vertices<W, CAP, 16>(S, p, nl); break;
+    case 32: fit_vertices<W, CAP, 32>(S, p, nl); break;
+    default: fit_vertices<W, CAP, 64>(S, p, nl); break;
     }
     __syncthreads();
+    stamp<DEBUG>(ts, 6);
 
     // final selection (Table 2, end of Sec. 3.5)
     if (wave == 0) {
@@ -766,73 +1078,17 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
             S.n_keep = kept;
     }
     __syncthreads();
+    stamp<DEBUG>(ts, 7);
 
     // final weights, vertex records
-    for (int k0 = 0; k0 < nl; k0 += G) {
-        const int k = k0 + gid;
-        const bool has = k < nl;
-        const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
-        const int vo = has ? S.vout[k] : -1;
-        const float dx = has ? S.vdx[k] : 0.0f, dy = has ? S.vdy[k] : 0.0f, dz = has ? S.vdz[k] : 0.0f;
-        float schi = 0.0f, sw = 0.0f;
-        for (int t = gl; t < ck; t += L) {
-            const int sl = beg + t;
-            const float wt = S.u.f.WT[sl];
-            float w = 0.0f, chi2 = 0.0f;
-            if (wt > 0.0f) {
-                const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
-                const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
-                chi2 = wt * fmaf(rx, rx, ry * ry);
-                if (chi2 < p.chi2_max) {
-                    const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
-                    w = u * u;
-                }
-            }
-            schi = fmaf(w, chi2, schi);
-            sw += w;
-            const int g = a + S.u.f.IDX[sl];
-            A.trk_vtx[g] = vo;
-            A.trk_w[g] = (vo >= 0) ? w : 0.0f;
-        }
-        schi = group_sum(schi, L);
-        sw = group_sum(sw, L);
-        if (has && gl == 0 && vo >= 0) {
-            const int cq = S.live[k];
-            const float zr = bin_centre(S.cpk[cq], p);
-            const float la = S.va[k], lb = S.vb[k], lc = S.vc[k], ld = S.vd[k];
-            float cf[6];
-            const float det = inverse_a<float>(la, lb, lc, ld, cf);
-            // 1-norm condition number of A
-            const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
-            const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
-                                         fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
-                                   fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
-            int flags = (S.vinfo[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
-            if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
-                double cd[6];
-                inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
-                for (int q = 0; q < 6; ++q)
-                    cf[q] = (float)cd[q];
-                flags |= PV_VX_FP64_INVERSION;
-            }
-            pv_vertex v;
-            v.x = (p.bx + p.btx * zr) + dx;
-            v.y = (p.by + p.bty * zr) + dy;
-            v.z = zr + dz;
-            for (int q = 0; q < 6; ++q)
-                v.cov[q] = cf[q];
-            v.chi2 = schi;
-            v.ndof = 2.0f * sw - 3.0f;
-            v.z_seed = zr + S.cd0[cq];
-            v.n_tracks = S.cnt[k];
-            v.bin_lo = S.clo[cq];
-            v.bin_hi = S.chi[cq];
-            v.peak_bin = S.cpk[cq];
-            v.n_iter = (uint8_t)(S.vinfo[k] & 0xFF);
-            v.flags = (uint8_t)flags;
-            v.reserved = 0;
-            A.vout[(size_t)e * p.max_vertices + vo] = v;
-        }
+    switch (L) {
+    case 1: final_pass<W, CAP, 1>(S, A, e, a, nl); break;
+    case 2: final_pass<W, CAP, 2>(S, A, e, a, nl); break;
+    case 4: final_pass<W, CAP, 4>(S, A, e, a, nl); break;
+    case 8: final_pass<W, CAP, 8>(S, A, e, a, nl); break;
+    case 16: final_pass<W, CAP, 16>(S, A, e, a, nl); break;
+    case 32: final_pass<W, CAP, 32>(S, A, e, a, nl); break;
+    default: final_pass<W, CAP, 64>(S, A, e, a, nl); break;
     }
     if (tid == 0) {
         A.nv_out[e] = S.n_keep;
@@ -841,6 +1097,10 @@ __device__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
             A.dbg_ncl[e] = S.n_cl;
     }
     __syncthreads();
+    stamp<DEBUG>(ts, 8);
+    if (DEBUG && A.dbg_cycles && tid == 0)
+        for (int k = 0; k < 8; ++k)
+            A.dbg_cycles[(size_t)e * 8 + k] = (uint32_t)(ts.t[k + 1] - ts.t[k]);
 }
 
 // mode 0: one workgroup per event (grid = n_events); mode 1: persistent grid

@@ -61,7 +61,8 @@ class pv_track_out(ctypes.Structure):
 
 class pv_debug_out(ctypes.Structure):
     _fields_ = [("hist", ctypes.c_void_p), ("clusters", ctypes.c_void_p), ("n_clusters", ctypes.c_void_p),
-                ("zpoca", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("bin", ctypes.c_void_p)]
+                ("zpoca", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("bin", ctypes.c_void_p),
+                ("stage_cycles", ctypes.c_void_p)]
 
 
 class pv_schedule(ctypes.Structure):
@@ -248,6 +249,7 @@ class DebugOutputs:
     zpoca: "object"
     sigma: "object"
     bin: "object"
+    stage_cycles: "object"
 
 
 def pv_find_debug(db: DeviceBatch, out: Outputs, params: pv_params, schedule: Optional[pv_schedule] = None,
@@ -261,9 +263,10 @@ def pv_find_debug(db: DeviceBatch, out: Outputs, params: pv_params, schedule: Op
                      n_clusters=torch.empty(ne, dtype=torch.int32, device=dev),
                      zpoca=torch.empty(nt, dtype=torch.float32, device=dev),
                      sigma=torch.empty(nt, dtype=torch.float32, device=dev),
-                     bin=torch.empty(nt, dtype=torch.int32, device=dev))
+                     bin=torch.empty(nt, dtype=torch.int32, device=dev),
+                     stage_cycles=torch.zeros(ne * 8, dtype=torch.int32, device=dev))
     dbg = pv_debug_out(d.hist.data_ptr(), d.clusters.data_ptr(), d.n_clusters.data_ptr(), d.zpoca.data_ptr(),
-                       d.sigma.data_ptr(), d.bin.data_ptr())
+                       d.sigma.data_ptr(), d.bin.data_ptr(), d.stage_cycles.data_ptr())
     tr, bl, ov, ot = _args(db, out, params)
     st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
     _check(lib().pv_find_debug(ctypes.byref(tr), ctypes.c_void_p(db.offsets.data_ptr()), db.n_events,
@@ -285,6 +288,7 @@ class HostResult:
     zpoca: Optional[np.ndarray] = None
     sigma: Optional[np.ndarray] = None
     bin: Optional[np.ndarray] = None
+    stage_cycles: Optional[np.ndarray] = None
 
 
 def to_host(db: DeviceBatch, out: Outputs, dbg: Optional[DebugOutputs] = None, nb: int = 0) -> HostResult:
@@ -299,6 +303,7 @@ def to_host(db: DeviceBatch, out: Outputs, dbg: Optional[DebugOutputs] = None, n
         r.zpoca = dbg.zpoca.cpu().numpy()[:nt]
         r.sigma = dbg.sigma.cpu().numpy()[:nt]
         r.bin = dbg.bin.cpu().numpy()[:nt]
+        r.stage_cycles = dbg.stage_cycles.cpu().numpy()[:ne * 8].view(np.uint32).reshape(ne, 8)
     return r
 
 
