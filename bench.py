@@ -46,6 +46,66 @@ def algorithmic_bytes(n_tracks, n_events, n_vertices):
     return 32 * n_tracks + 4 * n_events + 8 * n_tracks + 64 * n_vertices + 8 * n_events
 
 
+def latency_summary(comp, warm_frac=0.01):
+    k = int(len(comp) * warm_frac)
+    order = np.argsort(comp["t_arrival_ns"])
+    c = comp[order][k:]
+    lat = (c["t_done_ns"] - c["t_arrival_ns"]) / 1e3
+    span = (comp["t_done_ns"].max() - comp["t_arrival_ns"].min()) / 1e9
+    return {"p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "achieved_events_per_s": round(len(comp) / span, 1)}
+
+
+def served_leg(pv, synth, n_events):
+    """Continuous-batching server vs the plain one-launch-per-event server on
+    the served mix (mu log-uniform in [1, 40]), host buffers in and out, so
+    every figure includes the PCIe transfers."""
+    batch = synth.generate("served_mulog_200kev", n_events=n_events, keep_truth=False)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    rng = np.random.default_rng(7)
+    unit = rng.exponential(1.0, n_events)
+
+    def offsets(rate):
+        return np.cumsum(unit * (1e9 / rate)).astype(np.int64)
+
+    cfg = pv.pv_server_config_default(max_events_per_batch=1024, max_tracks_per_batch=1024 * 600, n_slots=6,
+                                      n_streams=3, max_wait_us=100, use_graphs=1)
+    plain_cfg = pv.pv_server_config_default(max_events_per_batch=1, max_tracks_per_batch=4096, n_slots=8,
+                                            n_streams=4, max_wait_us=0, use_graphs=1)
+    out = {"workload": "served_mulog_200kev", "events": n_events, "tracks": batch.n_tracks,
+           "config": {"max_events_per_batch": 1024, "slots": 6, "streams": 3, "max_wait_us": 100, "graphs": 1}}
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        srv.replay(host, np.zeros(min(n_events, 2048), dtype=np.int64)[:n_events])   # warm-up
+        comp = srv.replay(host, np.zeros(n_events, dtype=np.int64))
+        cap = latency_summary(comp)["achieved_events_per_s"]
+        out["capacity_events_per_s"] = cap
+        rates = []
+        for f in (0.5, 0.8, 0.95):
+            comp = srv.replay(host, offsets(f * cap))
+            rates.append(dict(offered_events_per_s=round(f * cap, 1), **latency_summary(comp)))
+        out["rates"] = rates
+        out["stats"] = srv.stats()
+    log(f"served capacity {cap:.4g} events/s; " + ", ".join(f"{r['offered_events_per_s']:.3g}/s: p50 {r['p50_us']} us "
+                                                          f"p99 {r['p99_us']} us" for r in rates))
+    n_plain = min(n_events, 4000)
+    sub = batch.select(range(n_plain))
+    hp = pv.HostEvents(sub, params.max_vertices_per_event)
+    with pv.Server(params, batch.beamline, plain_cfg) as srv:
+        comp = srv.replay(hp, np.zeros(n_plain, dtype=np.int64))
+        pcap = latency_summary(comp)["achieved_events_per_s"]
+        rate = 0.5 * pcap
+        comp = srv.replay(hp, np.cumsum(unit[:n_plain] * (1e9 / rate)).astype(np.int64))
+        plain = dict(capacity_events_per_s=pcap, offered_events_per_s=round(rate, 1), **latency_summary(comp))
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(hp, np.cumsum(unit[:n_plain] * (1e9 / rate)).astype(np.int64))
+        plain["batched_server_at_same_rate"] = latency_summary(comp)
+    out["plain_per_event"] = plain
+    log(f"plain per-event server capacity {pcap:.4g} events/s; at {rate:.3g}/s p50 {plain['p50_us']} us "
+        f"p99 {plain['p99_us']} us (batched server: p99 {plain['batched_server_at_same_rate']['p99_us']} us)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +117,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="waves,capacity,persistent,teams_per_cu")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--served-events", type=int, default=20000,
+                    help="events of the served mix replayed per offered rate (0 skips the served leg)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -86,6 +150,16 @@ def main():
     s = pv.pv_get_schedule()
     schedule = dict(waves_per_team=s.waves_per_team, track_capacity=s.track_capacity, persistent=s.persistent,
                     teams_per_cu=s.teams_per_cu)
+
+    if args.calibrate_copy_mib > 0:
+        # a plain copy kernel reading and writing a known number of bytes
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + written")
+        del src, dst
 
     db = pv.to_device(batch, dev)
     out = pv.alloc_outputs(db, params.max_vertices_per_event, dev)
@@ -191,13 +265,17 @@ def main():
                          f"{dt:.1f} s wall, OpenMP over events"}
         log(f"cpu oracle: {cpu['value']} events/s on {threads} threads")
 
+    served = None
+    if args.served_events > 0:
+        served = served_leg(pv, synth, args.served_events)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
                    "n_vertices": nv, "schedule": schedule},
-        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event,
+        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event, "served": served,
     }
     print(json.dumps(line), flush=True)
 

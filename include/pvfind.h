@@ -205,6 +205,27 @@ int pv_find_debug(const pv_tracks *tracks, const int32_t *event_offsets, int32_t
                   pv_vertices_out *out_vertices, pv_track_out *out_track_weights,
                   const pv_debug_out *debug, const pv_schedule *schedule, void *stream);
 
+/* Autotuner for the batched form: runs pv_find on the caller's batch with
+ * every schedule (waves_per_team x track_capacity x persistent), times
+ * `reps` launches of each with HIP events on `stream`, and makes the fastest
+ * the process-wide default.  Arguments as for pv_find; the outputs are
+ * overwritten (they end up holding the result of the winning schedule, which
+ * equals every other schedule's in its integer outputs).
+ *  reps       : timed launches per schedule, >= 1.
+ *  cache_path : text file keeping one line per (device, key); NULL for none.
+ *               With an entry for (device, key) and force == 0 nothing is
+ *               timed: the cached schedule becomes the default.
+ *  key        : caller's name for the workload shape (no tabs/newlines).
+ *  best       : receives the chosen schedule; may be NULL.
+ *  best_us    : receives its time per launch in microseconds (0 when read
+ *               from the cache); may be NULL.
+ * Synchronises `stream`. */
+int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                const pv_beamline *beamline, const pv_params *params,
+                pv_vertices_out *out_vertices, pv_track_out *out_track_weights, int32_t reps,
+                const char *cache_path, const char *key, int32_t force, pv_schedule *best,
+                double *best_us, void *stream);
+
 /* Replace / read the default schedule used by pv_find (process-wide). */
 int pv_set_schedule(const pv_schedule *schedule);
 int pv_get_schedule(pv_schedule *schedule);
@@ -218,6 +239,96 @@ int pv_get_schedule(pv_schedule *schedule);
  * output pointer may be NULL). */
 int pv_timing_start(void);
 int pv_timing_stop(double *main_ms, double *large_ms, int64_t *n_calls);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of events that arrive one at a time.
+ *
+ * The paper processes batches of events on several streams so that
+ * transfers overlap compute (Sec. 6).  A server owns a fixed pool of batch
+ * slots, each with pinned host staging, device buffers and (optionally) an
+ * instantiated hipGraph of the pv_find launches; the graphs read the batch
+ * size from device memory, so one graph serves every batch of its slot.
+ * pv_server_submit copies an event into the slot that is open for
+ * admission; a worker thread seals the open batch as soon as a stream is
+ * free (or the oldest event has waited max_wait_us), copies it in, launches,
+ * copies the results out and scatters them into the caller's host buffers.
+ * Events that arrive while others are on the GPU join the next batch.
+ * Admission is bounded by the slot pool (sized against the device-memory
+ * budget): when every slot is busy, submit returns PV_EBUSY.
+ * A server with max_events_per_batch = 1 is the plain one-launch-per-event
+ * form on the same machinery.  Every event's result does not depend on the
+ * batch it was processed in.
+ * ------------------------------------------------------------------------ */
+typedef struct pv_server pv_server;
+
+typedef struct {
+    int32_t max_events_per_batch;   /* events per batch slot, >= 1                   */
+    int32_t max_tracks_per_batch;   /* tracks per batch slot; also the largest event  */
+    int32_t n_slots;                /* batch slots (staging + device buffers), >= 2   */
+    int32_t n_streams;              /* HIP streams, >= 1; batches in flight <= this   */
+    int64_t device_budget_bytes;    /* the slots' device memory must fit in this      */
+    int32_t max_wait_us;            /* seal a waiting batch after this long even when
+                                       every stream is busy                            */
+    int32_t use_graphs;             /* 1: launch batches as hipGraphs; 0: launches    */
+} pv_server_config;
+
+typedef struct {
+    const float *x, *y, *z, *tx, *ty, *cov_xx, *cov_xtx, *cov_txtx;   /* HOST, n_tracks each;
+                                       read before pv_server_submit returns            */
+    int32_t n_tracks;
+    pv_vertex *vertices;            /* HOST, max_vertices_per_event records           */
+    int32_t *track_vertex;          /* HOST, n_tracks                                 */
+    float *track_weight;            /* HOST, n_tracks                                 */
+} pv_request;                       /* output buffers stay the caller's; they are
+                                       written before the event is reported complete  */
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;                 /* PV_EV_* bits                                   */
+    int32_t n_vertices;
+    int64_t t_arrival_ns;           /* steady clock, see pv_clock_ns                  */
+    int64_t t_done_ns;              /* when the results were in the caller's buffers  */
+} pv_completion;
+
+typedef struct {
+    int64_t submitted, completed, rejected_busy, batches;
+    double mean_batch_events;
+    int64_t device_bytes;           /* device memory held by the slots               */
+} pv_server_stats;
+
+/* Steady-clock nanoseconds used for arrival and completion stamps. */
+int64_t pv_clock_ns(void);
+
+void pv_server_config_default(pv_server_config *c);
+
+/* Create a server on the current device.  schedule may be NULL (default).
+ * Returns PV_EINVAL for bad arguments or when the slots do not fit in the
+ * budget, PV_ENOMEM / PV_EHIP on allocation or capture failures. */
+int pv_server_create(pv_server **out, const pv_params *params, const pv_beamline *beamline,
+                     const pv_server_config *config, const pv_schedule *schedule);
+
+/* Admit one event.  t_arrival_ns = 0 stamps the current time.
+ * PV_EBUSY: no batch slot can take it now (retry later); PV_EINVAL: the
+ * event has more tracks than a slot holds or a null pointer. */
+int pv_server_submit(pv_server *s, const pv_request *req, uint64_t tag, int64_t t_arrival_ns);
+
+/* Move up to max_out completions into out, waiting up to timeout_us for the
+ * first one.  Returns the number moved (>= 0) or a negative PV_E* code. */
+int pv_server_poll(pv_server *s, pv_completion *out, int32_t max_out, int32_t timeout_us);
+
+/* Wait until every admitted event is complete (timeout_ms < 0: no limit).
+ * Returns PV_OK, or PV_EBUSY on timeout. */
+int pv_server_drain(pv_server *s, int32_t timeout_ms);
+
+/* Submit reqs[k] at arrival time t0 + t_offset_ns[k] (t0 = call time),
+ * retrying while the server is busy, and collect every completion:
+ * out[k] is the completion of reqs[k] (tag = k).  Returns when all n are
+ * complete. */
+int pv_server_replay(pv_server *s, const pv_request *reqs, const int64_t *t_offset_ns, int32_t n,
+                     pv_completion *out);
+
+int pv_server_get_stats(pv_server *s, pv_server_stats *stats);
+int pv_server_destroy(pv_server *s);
 
 /* Thread-local description of the last non-zero return of this thread. */
 const char *pv_last_error(void);

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpvfind.so")
-SOURCES = [os.path.join(CSRC, "pvfind_kernels.hip"), os.path.join(CSRC, "pvfind_api.cpp")]
+SOURCES = [os.path.join(CSRC, "pvfind_kernels.hip"), os.path.join(CSRC, "pvfind_api.cpp"),
+           os.path.join(CSRC, "pvfind_server.cpp")]
 ARCH = os.environ.get("PV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -28,6 +29,7 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay off (some of their forms misbehave)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-pthread",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -6,6 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -284,6 +287,37 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
 
 }  // namespace
 
+namespace pvk {
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int derive_kparams(const pv_params *p, const pv_beamline *bl, KParams &k)
+{
+    if (!p || !bl)
+        return fail(PV_EINVAL, "null params or beamline");
+    return derive_params(p, bl, k);
+}
+
+int schedule_for(const pv_schedule *requested, pv_schedule &out)
+{
+    out = resolve_schedule(requested);
+    return validate_schedule(out);
+}
+
+int workspace_for(void *stream, int n_events, WorkQueue **out)
+{
+    return get_workspace(stream, n_events, out);
+}
+
+}  // namespace pvk
+
 extern "C" {
 
 void pv_params_default(pv_params *p)
@@ -349,6 +383,147 @@ int pv_find_debug(const pv_tracks *tracks, const int32_t *event_offsets, int32_t
         return fail(PV_EINVAL, "null debug argument");
     return find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights, debug,
                      schedule, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string s = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    for (char &c : s)
+        if (c == '\t' || c == '\n' || c == ' ')
+            c = '_';
+    return s;
+}
+
+bool read_cache(const char *path, const std::string &dev, const std::string &key, pv_schedule &out)
+{
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream ls(line);
+        std::string d, k;
+        pv_schedule s;
+        double us;
+        if (std::getline(ls, d, '\t') && std::getline(ls, k, '\t') &&
+            (ls >> s.waves_per_team >> s.track_capacity >> s.persistent >> s.teams_per_cu >> us) && d == dev &&
+            k == key && validate_schedule(s) == PV_OK) {
+            out = s;   // the last matching line wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                const pv_beamline *beamline, const pv_params *params, pv_vertices_out *out_vertices,
+                pv_track_out *out_track_weights, int32_t reps, const char *cache_path, const char *key,
+                int32_t force, pv_schedule *best, double *best_us, void *stream)
+{
+    if (reps < 1)
+        return fail(PV_EINVAL, "autotune: reps must be >= 1");
+    if (cache_path && !key)
+        return fail(PV_EINVAL, "autotune: a cache needs a key");
+    if (key && (std::strchr(key, '\t') || std::strchr(key, '\n')))
+        return fail(PV_EINVAL, "autotune: key must not contain tabs or newlines");
+    const std::string dev = device_tag();
+    pv_schedule chosen{};
+    double chosen_us = 0.0;
+    if (cache_path && !force && read_cache(cache_path, dev, key, chosen)) {
+        int rc = pv_set_schedule(&chosen);
+        if (rc == PV_OK) {
+            if (best)
+                *best = chosen;
+            if (best_us)
+                *best_us = 0.0;
+        }
+        return rc;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return fail(PV_EHIP, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(PV_EHIP, "hipEventCreate failed");
+    }
+    int rc = PV_OK;
+    bool have = false;
+    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[2] = {1, 2};
+    for (int w : waves)
+        for (int c : caps)
+            for (int m : modes) {
+                if (rc != PV_OK)
+                    break;
+                const pv_schedule s = {w, c, m, 0};
+                rc = find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights,
+                               nullptr, &s, stream);   // warm-up, also validates the arguments
+                if (rc != PV_OK)
+                    break;
+                hipError_t err = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && rc == PV_OK && err == hipSuccess; ++r)
+                    rc = find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices,
+                                   out_track_weights, nullptr, &s, stream);
+                if (rc != PV_OK)
+                    break;
+                if (err == hipSuccess)
+                    err = hipEventRecord(e1, st);
+                if (err == hipSuccess)
+                    err = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (err == hipSuccess)
+                    err = hipEventElapsedTime(&ms, e0, e1);
+                if (err != hipSuccess) {
+                    rc = fail(PV_EHIP, "autotune timing: %s", hipGetErrorString(err));
+                    break;
+                }
+                const double us = 1e3 * (double)ms / reps;
+                if (!have || us < chosen_us) {
+                    chosen = s;
+                    chosen_us = us;
+                    have = true;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PV_OK || !have)
+        return rc != PV_OK ? rc : fail(PV_EINVAL, "autotune: nothing timed");
+    // leave the winner's results in the outputs
+    rc = find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights, nullptr,
+                   &chosen, stream);
+    if (rc == PV_OK) {
+        const hipError_t err = hipStreamSynchronize(st);
+        if (err != hipSuccess)
+            rc = fail(PV_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(err));
+    }
+    if (rc != PV_OK)
+        return rc;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (!f)
+            return fail(PV_EINVAL, "autotune: cannot append to %s", cache_path);
+        f << dev << '\t' << key << '\t' << chosen.waves_per_team << ' ' << chosen.track_capacity << ' '
+          << chosen.persistent << ' ' << chosen.teams_per_cu << ' ' << chosen_us << '\n';
+    }
+    rc = pv_set_schedule(&chosen);
+    if (rc == PV_OK) {
+        if (best)
+            *best = chosen;
+        if (best_us)
+            *best_us = chosen_us;
+    }
+    return rc;
 }
 
 int pv_set_schedule(const pv_schedule *schedule)

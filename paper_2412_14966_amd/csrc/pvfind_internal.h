@@ -48,7 +48,8 @@ struct WorkQueue {
 struct KArgs {
     const float *x, *y, *z, *tx, *ty, *cxx, *cxtx, *ctxtx;
     const int32_t *offsets;
-    int32_t n_events;
+    int32_t n_events;               // events of the batch, or the capacity when n_events_dev is set
+    const int32_t *n_events_dev;    // when set, the batch size is read from device memory (graph replay)
     pv_vertex *vout;
     int32_t *nv_out;
     int32_t *status_out;
@@ -70,6 +71,12 @@ struct LaunchEvents {
     void *large_begin = nullptr, *large_end = nullptr;  // hipEvent_t, unused when no large launch
     bool large = false;
 };
+
+// Host helpers shared by the C ABI files (pvfind_api.cpp).
+int set_error(int code, const char *fmt, ...);
+int derive_kparams(const pv_params *p, const pv_beamline *bl, KParams &k);
+int schedule_for(const pv_schedule *requested, pv_schedule &out);
+int workspace_for(void *stream, int n_events, WorkQueue **out);
 
 // Launch one batch on `stream` with schedule `s` (already validated).  With
 // `ev`, events are recorded around the launches.  Returns a hipError_t value.

@@ -290,8 +290,14 @@ __device__ __forceinline__ int argmax_bins(const int *h, int s, int e)
 // with bin total `tot`.  Returns the number of clusters; with `write` stores
 // them from index `first`.
 // ---------------------------------------------------------------------------
+// Without `write`, the first four split points (cluster ends) are also
+// packed into *cuts (16 bits each), their count into *nsplit and whether the
+// remainder is a cluster into *fin, so the clusters can be written without a
+// second walk.
 template <int W, int CAP>
-__device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, int tot, bool write, int first)
+__device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, int tot, bool write,
+                                          int first, unsigned long long *cuts = nullptr, int *nsplit = nullptr,
+                                          int *fin = nullptr)
 {
     const int *h = S.u.hist;
     const bool strad = (s < p.gas_bin) && (e >= p.gas_bin);
@@ -312,7 +318,8 @@ __device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int
         }
         ++count;
     };
-    int cs = s, pcs = 0;
+    int cs = s, pcs = 0, ns = 0;
+    unsigned long long cw = 0ull;
     int up = 1, M = 0, m = 0, mj = s, pm = 0, pref = 0;
     for (int k0 = s; k0 <= e; k0 += 8) {
         int v[8];
@@ -345,6 +352,9 @@ __device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int
                 } else if (hk >= m + p.dip_prom) {
                     if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
                         emit(cs, mj);
+                        if (ns < 4)
+                            cw |= (unsigned long long)(unsigned)mj << (16 * ns);
+                        ++ns;
                         cs = mj + 1;
                         pcs = pm;
                     }
@@ -354,8 +364,14 @@ __device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int
             }
         }
     }
-    if (tot - pcs >= thr(cs, e))
+    const bool last = tot - pcs >= thr(cs, e);
+    if (last)
         emit(cs, e);
+    if (cuts) {
+        *cuts = cw;
+        *nsplit = ns;
+        *fin = last ? 1 : 0;
+    }
     return count;
 }
 
@@ -428,10 +444,32 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
                 e = S.pe[lane];
             }
             const int tot = has ? sum_bins(S.u.hist, s, e) : 0;
-            const int c = has ? walk_proto(S, p, s, e, tot, false, 0) : 0;
+            unsigned long long cw = 0ull;
+            int ns = 0, fin = 0;
+            const int c = has ? walk_proto(S, p, s, e, tot, false, 0, &cw, &ns, &fin) : 0;
             const int incl = wave_incl_scan(c, lane);
-            if (has)
-                walk_proto(S, p, s, e, tot, true, n_found + incl - c);
+            const int first = n_found + incl - c;
+            if (has && ns > 4) {
+                walk_proto(S, p, s, e, tot, true, first);   // rare: more splits than recorded
+            } else if (has) {
+                int lo = s, q = first;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k < ns) {
+                        const int hi = (int)((cw >> (16 * k)) & 0xFFFFull);
+                        if (q < p.max_vertices) {
+                            S.clo[q] = (short)lo;
+                            S.chi[q] = (short)hi;
+                        }
+                        ++q;
+                        lo = hi + 1;
+                    }
+                }
+                if (fin && q < p.max_vertices) {
+                    S.clo[q] = (short)lo;
+                    S.chi[q] = (short)e;
+                }
+            }
             n_found += __shfl(incl, 63);
             npend = 0;
             __builtin_amdgcn_wave_barrier();
@@ -718,13 +756,13 @@ __device__ __forceinline__ void stamp(Stamps &st, int k)
 // one event
 // ---------------------------------------------------------------------------
 template <int W, int CAP, bool BIG, bool DEBUG>
-__device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e)
+__device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e, int n_events)
 {
     constexpr int NT = 64 * W;
     const KParams &p = A.p;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    const int a = A.offsets[e], b = A.offsets[e + 1], total = A.offsets[A.n_events];
+    const int a = A.offsets[e], b = A.offsets[e + 1], total = A.offsets[n_events];
     const bool bad_offsets = (a < 0) || (b < a) || (b > total);
     const int n = bad_offsets ? 0 : b - a;
     if (bad_offsets || n > p.max_tracks) {
@@ -981,13 +1019,19 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             S.wrun[0][k] = S.base[k];
         __syncthreads();
     }
+    float gnext[8];
+    if (r0 + lane < r1)
+        load_track(A, a + r0 + lane, gnext);
     for (int c0 = r0; c0 < r1; c0 += 64) {
         const int i = c0 + lane;
         const bool valid = i < r1;
         const int own = valid ? (S.tb[i] >> 16) - 1 : -1;
         float t[8];
-        if (own >= 0)
-            load_track(A, a + i, t);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            t[q] = gnext[q];
+        if (c0 + 64 + lane < r1)
+            load_track(A, a + c0 + 64 + lane, gnext);
         unsigned long long rem = __ballot(own >= 0);
         int slot = -1;
         while (rem) {
@@ -1110,6 +1154,7 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
 {
     __shared__ Smem<W, CAP> S;
     const int tid = threadIdx.x;
+    const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
     bool first = true;
     for (;;) {
         if (tid == 0) {
@@ -1121,9 +1166,9 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
                     e = A.wq->big[k];
             } else if (mode == 1) {
                 const unsigned int k = atomicAdd(&A.wq->next, 1u);
-                if (k < (unsigned int)A.n_events)
+                if (k < (unsigned int)n_events)
                     e = (int)k;
-            } else if (first) {
+            } else if (first && (int)blockIdx.x < n_events) {
                 e = (int)blockIdx.x;
             }
             S.ev = e;
@@ -1134,7 +1179,7 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
         __syncthreads();
         if (e < 0)
             break;
-        process_event<W, CAP, BIG, DEBUG>(S, A, e);
+        process_event<W, CAP, BIG, DEBUG>(S, A, e, n_events);
     }
     if (tid == 0 && (BIG || mode == 1)) {
         __threadfence();
@@ -1163,7 +1208,8 @@ struct DevInfo {
 
 static int device_cus()
 {
-    static int cached_dev = -1, cached_cus = 0;
+    // per thread: the server's worker thread and callers may launch concurrently
+    static thread_local int cached_dev = -1, cached_cus = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return 0;
@@ -1213,8 +1259,9 @@ template <int W, int CAP, bool DEBUG>
 static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     hipError_t err = record(ev ? ev->main_begin : nullptr, st);
+    const int mode = (s.persistent == 1 || A.n_events_dev) ? 1 : 0;
     if (err == hipSuccess)
-        err = launch_one<W, CAP, false, DEBUG>(A, s.persistent == 1 ? 1 : 0, s.teams_per_cu, st);
+        err = launch_one<W, CAP, false, DEBUG>(A, mode, s.teams_per_cu, st);
     if (err == hipSuccess)
         err = record(ev ? ev->main_end : nullptr, st);
     if (err != hipSuccess)

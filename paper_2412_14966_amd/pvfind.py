@@ -102,6 +102,9 @@ def lib():
         L.pv_find_debug.argtypes = common + [P(pv_debug_out), P(pv_schedule), vp]
         for f in (L.pv_find, L.pv_find_sched, L.pv_find_debug):
             f.restype = ctypes.c_int
+        L.pv_autotune.argtypes = common + [ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int32,
+                                           P(pv_schedule), P(ctypes.c_double), vp]
+        L.pv_autotune.restype = ctypes.c_int
         L.pv_set_schedule.argtypes = [P(pv_schedule)]
         L.pv_get_schedule.argtypes = [P(pv_schedule)]
         L.pv_timing_start.argtypes = []
@@ -241,6 +244,22 @@ def pv_find_sched(db: DeviceBatch, out: Outputs, params: pv_params, schedule: pv
                                ctypes.byref(schedule), st))
 
 
+def pv_autotune(db: DeviceBatch, out: Outputs, params: pv_params, reps: int = 5, cache_path: Optional[str] = None,
+                key: Optional[str] = None, force: bool = False, stream=None):
+    """Time every schedule on this batch and make the fastest the default.
+    Returns (schedule dict, microseconds per launch; 0 when read from the cache)."""
+    tr, bl, ov, ot = _args(db, out, params)
+    st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
+    best = pv_schedule()
+    us = ctypes.c_double()
+    _check(lib().pv_autotune(ctypes.byref(tr), ctypes.c_void_p(db.offsets.data_ptr()), db.n_events,
+                             ctypes.byref(bl), ctypes.byref(params), ctypes.byref(ov), ctypes.byref(ot), int(reps),
+                             cache_path.encode() if cache_path else None, key.encode() if key else None,
+                             1 if force else 0, ctypes.byref(best), ctypes.byref(us), st))
+    return (dict(waves_per_team=best.waves_per_team, track_capacity=best.track_capacity,
+                 persistent=best.persistent, teams_per_cu=best.teams_per_cu), us.value)
+
+
 @dataclasses.dataclass
 class DebugOutputs:
     hist: "object"
@@ -325,3 +344,150 @@ def run(batch: synth.TrackBatch, params: Optional[Dict] = None, schedule: Option
         d = None
     torch.cuda.synchronize()
     return to_host(db, out, d, pv_nbins(p))
+
+
+# ---------------------------------------------------------------------------
+# serving (continuous batching), see pv_server_* in include/pvfind.h
+# ---------------------------------------------------------------------------
+class pv_server_config(ctypes.Structure):
+    _fields_ = [("max_events_per_batch", ctypes.c_int32), ("max_tracks_per_batch", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("device_budget_bytes", ctypes.c_int64), ("max_wait_us", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
+
+
+class pv_request(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("x", "y", "z", "tx", "ty", "cov_xx", "cov_xtx", "cov_txtx")] + \
+               [("n_tracks", ctypes.c_int32), ("vertices", ctypes.c_void_p), ("track_vertex", ctypes.c_void_p),
+                ("track_weight", ctypes.c_void_p)]
+
+
+class pv_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("n_vertices", ctypes.c_int32),
+                ("t_arrival_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class pv_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("mean_batch_events", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("status", "<i4"), ("n_vertices", "<i4"), ("t_arrival_ns", "<i8"),
+                             ("t_done_ns", "<i8")])
+assert COMPLETION_DTYPE.itemsize == ctypes.sizeof(pv_completion)
+
+_server_ready = False
+
+
+def _server_lib():
+    global _server_ready
+    L = lib()
+    if not _server_ready:
+        P = ctypes.POINTER
+        L.pv_clock_ns.restype = ctypes.c_int64
+        L.pv_server_config_default.argtypes = [P(pv_server_config)]
+        L.pv_server_config_default.restype = None
+        L.pv_server_create.argtypes = [P(ctypes.c_void_p), P(pv_params), P(pv_beamline), P(pv_server_config),
+                                       P(pv_schedule)]
+        L.pv_server_submit.argtypes = [ctypes.c_void_p, P(pv_request), ctypes.c_uint64, ctypes.c_int64]
+        L.pv_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+        L.pv_server_drain.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.pv_server_replay.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p]
+        L.pv_server_get_stats.argtypes = [ctypes.c_void_p, P(pv_server_stats)]
+        L.pv_server_destroy.argtypes = [ctypes.c_void_p]
+        _server_ready = True
+    return L
+
+
+def pv_server_config_default(**overrides) -> pv_server_config:
+    c = pv_server_config()
+    _server_lib().pv_server_config_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class HostEvents:
+    """Host-side requests for every event of a TrackBatch, with output arrays."""
+
+    def __init__(self, batch: synth.TrackBatch, max_vertices: int):
+        self.batch = batch
+        self.cols = [np.ascontiguousarray(c, dtype=np.float32) for c in batch.fields()]
+        ne, nt = batch.n_events, batch.n_tracks
+        self.vertices = np.zeros((max(ne, 1), max_vertices), dtype=VERTEX_DTYPE)
+        self.track_vertex = np.full(max(nt, 1), -7, dtype=np.int32)
+        self.track_weight = np.full(max(nt, 1), -7.0, dtype=np.float32)
+        self.requests = (pv_request * max(ne, 1))()
+        for e in range(ne):
+            a, n = int(batch.offsets[e]), int(batch.offsets[e + 1] - batch.offsets[e])
+            r = self.requests[e]
+            for k, name in enumerate(("x", "y", "z", "tx", "ty", "cov_xx", "cov_xtx", "cov_txtx")):
+                setattr(r, name, self.cols[k].ctypes.data + 4 * a)
+            r.n_tracks = n
+            r.vertices = self.vertices.ctypes.data + e * max_vertices * 64
+            r.track_vertex = self.track_vertex.ctypes.data + 4 * a
+            r.track_weight = self.track_weight.ctypes.data + 4 * a
+
+
+class Server:
+    """pv_server_*: continuous batching of events submitted from the host."""
+
+    def __init__(self, params: pv_params, beamline=(0.0, 0.0, 0.0, 0.0), config: Optional[pv_server_config] = None,
+                 schedule: Optional[pv_schedule] = None):
+        L = _server_lib()
+        self.params = params
+        self.config = config or pv_server_config_default()
+        h = ctypes.c_void_p()
+        bl = pv_beamline(*[float(v) for v in beamline])
+        _check(L.pv_server_create(ctypes.byref(h), ctypes.byref(params), ctypes.byref(bl),
+                                  ctypes.byref(self.config), ctypes.byref(schedule) if schedule else None))
+        self.handle = h
+
+    def submit(self, req: pv_request, tag: int, t_arrival_ns: int = 0) -> int:
+        """Returns PV_OK or PV_EBUSY; raises on other errors."""
+        rc = _server_lib().pv_server_submit(self.handle, ctypes.byref(req), tag, t_arrival_ns)
+        if rc not in (PV_OK, PV_EBUSY):
+            _check(rc)
+        return rc
+
+    def poll(self, max_out: int = 1024, timeout_us: int = 0) -> np.ndarray:
+        out = np.zeros(max_out, dtype=COMPLETION_DTYPE)
+        k = _server_lib().pv_server_poll(self.handle, out.ctypes.data, max_out, timeout_us)
+        if k < 0:
+            _check(k)
+        return out[:k]
+
+    def drain(self, timeout_ms: int = -1):
+        _check(_server_lib().pv_server_drain(self.handle, timeout_ms))
+
+    def replay(self, events: HostEvents, t_offset_ns: np.ndarray) -> np.ndarray:
+        n = events.batch.n_events
+        offs = np.ascontiguousarray(t_offset_ns, dtype=np.int64)
+        out = np.zeros(max(n, 1), dtype=COMPLETION_DTYPE)
+        _check(_server_lib().pv_server_replay(self.handle, ctypes.addressof(events.requests), offs.ctypes.data, n,
+                                              out.ctypes.data))
+        return out[:n]
+
+    def stats(self) -> dict:
+        st = pv_server_stats()
+        _check(_server_lib().pv_server_get_stats(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in pv_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(_server_lib().pv_server_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def pv_clock_ns() -> int:
+    return _server_lib().pv_clock_ns()

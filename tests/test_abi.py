@@ -122,3 +122,31 @@ def test_schedule_round_trip():
             pv.pv_set_schedule(5, 512, 1, 0)
     finally:
         pv.lib().pv_set_schedule(ctypes.byref(old))
+
+
+def test_server_and_autotune_reject_bad_arguments_on_the_host():
+    L = pv._server_lib()
+    p = pv.pv_params_default()
+    bl = pv.pv_beamline(0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    for bad in (dict(n_slots=1), dict(max_events_per_batch=0), dict(n_streams=5, n_slots=4),
+                dict(device_budget_bytes=1024), dict(max_wait_us=-1)):
+        cfg = pv.pv_server_config_default(**bad)
+        assert L.pv_server_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(bl), ctypes.byref(cfg),
+                                  None) == pv.PV_EINVAL, bad
+    cfg = pv.pv_server_config_default()
+    bad_p = pv.make_params({"max_iter": 0})
+    assert L.pv_server_create(ctypes.byref(h), ctypes.byref(bad_p), ctypes.byref(bl), ctypes.byref(cfg),
+                              None) == pv.PV_EINVAL
+    assert L.pv_server_submit(None, None, 0, 0) == pv.PV_EINVAL
+    assert L.pv_server_destroy(None) == pv.PV_OK
+    # autotune validates before touching the device
+    fake = 0x1000
+    tr = pv.pv_tracks(*([fake] * 8))
+    ov = pv.pv_vertices_out(fake, fake, fake)
+    ot = pv.pv_track_out(fake, fake)
+    args = (ctypes.byref(tr), ctypes.c_void_p(fake), 1, ctypes.byref(bl), ctypes.byref(p), ctypes.byref(ov),
+            ctypes.byref(ot))
+    assert L.pv_autotune(*args, 0, None, None, 0, None, None, None) == pv.PV_EINVAL
+    assert L.pv_autotune(*args, 3, b"/tmp/x", b"a\tb", 0, None, None, None) == pv.PV_EINVAL
+    assert L.pv_autotune(*args, 3, b"/tmp/x", None, 0, None, None, None) == pv.PV_EINVAL

@@ -1,0 +1,159 @@
+"""Serving (continuous batching) and the autotuner on the GPU.
+
+Each event's result must be the same whether it is processed alone, in a
+batched pv_find call or in the server's mix: the kernels process every event
+independently, so for a fixed schedule the outputs are bit-identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_14966_amd import pvfind as pv
+from paper_2412_14966_amd import synth
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pv.lib()
+    yield
+
+
+def poisson_offsets(n, rate_per_s, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1e9 / rate_per_s, n)).astype(np.int64)
+
+
+def check_same_as_batched(batch, host: "pv.HostEvents", ref: "pv.HostResult", comp, max_v):
+    assert len(comp) == batch.n_events
+    assert np.array_equal(comp["tag"], np.arange(batch.n_events))
+    assert np.array_equal(comp["n_vertices"], ref.n_vertices)
+    assert np.array_equal(comp["status"], ref.status)
+    assert np.array_equal(host.track_vertex[:batch.n_tracks], ref.track_vertex)
+    assert np.array_equal(host.track_weight[:batch.n_tracks].view(np.uint32), ref.track_weight.view(np.uint32))
+    for e in range(batch.n_events):
+        n = int(ref.n_vertices[e])
+        assert np.array_equal(host.vertices[e, :n].view(np.uint8), ref.vertices[e, :n].view(np.uint8)), e
+    assert np.all(comp["t_done_ns"] >= comp["t_arrival_ns"])
+
+
+@pytest.mark.parametrize("graphs", [1, 0])
+def test_served_mix_equals_batched_and_oracle(graphs):
+    batch = synth.generate("served_mulog_200kev", n_events=3000, keep_truth=False)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    say(f"served mix graphs={graphs}: {batch.n_events} events, {batch.n_tracks} tracks")
+    ref = pv.run(batch, pv.params_dict(params))
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=512, max_tracks_per_batch=512 * 600, n_slots=4,
+                                      n_streams=2, max_wait_us=100, use_graphs=graphs)
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, poisson_offsets(batch.n_events, 2.0e5, seed=graphs))
+        st = srv.stats()
+    say(f"served mix graphs={graphs}: stats {st}")
+    assert st["completed"] == batch.n_events and st["batches"] > 1
+    assert st["mean_batch_events"] > 1.0
+    check_same_as_batched(batch, host, ref, comp, params.max_vertices_per_event)
+    # and the same events against the oracle
+    o = oracle.find(batch, parity.oracle_params(params))
+    g = pv.HostResult(n_vertices=comp["n_vertices"].astype(np.int32), status=comp["status"].astype(np.int32),
+                      vertices=host.vertices[:batch.n_events], track_vertex=host.track_vertex[:batch.n_tracks],
+                      track_weight=host.track_weight[:batch.n_tracks])
+    rep = parity.compare(batch, g, o)
+    say(f"served mix vs oracle: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+
+
+def test_event_alone_equals_event_in_mix():
+    batch = synth.generate("served_mulog_200kev", n_events=400, keep_truth=False)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=128, max_tracks_per_batch=128 * 600, n_slots=3,
+                                      n_streams=2, max_wait_us=50)
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, np.zeros(batch.n_events, dtype=np.int64))   # all at once: large batches
+    for e in (0, 57, 399):
+        say(f"event {e} alone through a fresh server")
+        one = batch.event(e)
+        h1 = pv.HostEvents(one, params.max_vertices_per_event)
+        with pv.Server(params, one.beamline, cfg) as srv:
+            c1 = srv.replay(h1, np.zeros(1, dtype=np.int64))
+        n = int(comp["n_vertices"][e])
+        assert int(c1["n_vertices"][0]) == n
+        assert np.array_equal(h1.vertices[0, :n].view(np.uint8), host.vertices[e, :n].view(np.uint8))
+        a, b = batch.offsets[e], batch.offsets[e + 1]
+        assert np.array_equal(h1.track_weight[:b - a].view(np.uint32), host.track_weight[a:b].view(np.uint32))
+
+
+def test_plain_one_event_per_launch_server():
+    batch = synth.generate("served_mulog_200kev", n_events=200, keep_truth=False)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    ref = pv.run(batch, pv.params_dict(params))
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=1, max_tracks_per_batch=4096, n_slots=8, n_streams=4,
+                                      max_wait_us=0)
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, poisson_offsets(batch.n_events, 2e4))
+        st = srv.stats()
+    assert st["batches"] == batch.n_events and st["mean_batch_events"] == 1.0
+    check_same_as_batched(batch, host, ref, comp, params.max_vertices_per_event)
+
+
+def test_back_pressure_and_oversized_events():
+    batch = synth.generate("served_mulog_200kev", n_events=300, keep_truth=False)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    ref = pv.run(batch, pv.params_dict(params))
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=4, max_tracks_per_batch=8000, n_slots=2, n_streams=1,
+                                      max_wait_us=1000)
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        # oversized: more tracks than a slot holds
+        big = synth.generate("pp_mu40_20kev", n_events=1, mu=400.0, keep_truth=False)
+        hb = pv.HostEvents(big, params.max_vertices_per_event)
+        if big.n_tracks > 8000:
+            with pytest.raises(pv.PvError):
+                srv.submit(hb.requests[0], 999)
+        comp = srv.replay(host, np.zeros(batch.n_events, dtype=np.int64))
+        st = srv.stats()
+    say(f"back-pressure stats {st}")
+    assert st["rejected_busy"] > 0 and st["completed"] == batch.n_events
+    check_same_as_batched(batch, host, ref, comp, params.max_vertices_per_event)
+
+
+def test_autotune_picks_a_schedule_and_keeps_results(tmp_path):
+    import torch
+    batch = synth.generate("pp_mu5_10kev", n_events=2000, keep_truth=False)
+    p = pv.pv_params_default()
+    old = pv.pv_get_schedule()
+    try:
+        db = pv.to_device(batch)
+        out = pv.alloc_outputs(db, p.max_vertices_per_event)
+        cache = str(tmp_path / "tune.txt")
+        best, us = pv.pv_autotune(db, out, p, reps=3, cache_path=cache, key="mu5_2k")
+        torch.cuda.synchronize()
+        say(f"autotune: {best} {us:.1f} us")
+        assert us > 0
+        r = pv.to_host(db, out)
+        ref = pv.run(batch, schedule=best)
+        assert np.array_equal(r.track_vertex, ref.track_vertex)
+        assert np.array_equal(r.track_weight.view(np.uint32), ref.track_weight.view(np.uint32))
+        # a second call reads the cache and times nothing
+        best2, us2 = pv.pv_autotune(db, out, p, reps=3, cache_path=cache, key="mu5_2k")
+        assert best2 == best and us2 == 0.0
+        s = pv.pv_get_schedule()
+        assert (s.waves_per_team, s.track_capacity, s.persistent) == (best["waves_per_team"],
+                                                                    best["track_capacity"], best["persistent"])
+    finally:
+        pv.lib().pv_set_schedule(pv.ctypes.byref(old))
