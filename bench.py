@@ -75,15 +75,19 @@ def served_leg(pv, synth, n_events):
                                             n_streams=4, max_wait_us=0, use_graphs=1)
     out = {"workload": "served_mulog_200kev", "events": n_events, "tracks": batch.n_tracks,
            "config": {"max_events_per_batch": 1024, "slots": 6, "streams": 3, "max_wait_us": 100, "graphs": 1}}
+    warm = batch.select(range(min(n_events, 2048)))
+    hw = pv.HostEvents(warm, params.max_vertices_per_event)
     with pv.Server(params, batch.beamline, cfg) as srv:
-        srv.replay(host, np.zeros(min(n_events, 2048), dtype=np.int64)[:n_events])   # warm-up
+        srv.replay(hw, np.zeros(warm.n_events, dtype=np.int64))   # warm-up
         comp = srv.replay(host, np.zeros(n_events, dtype=np.int64))
         cap = latency_summary(comp)["achieved_events_per_s"]
+        log(f"served capacity (all {n_events} events at once): {cap:.4g} events/s")
         out["capacity_events_per_s"] = cap
         rates = []
         for f in (0.5, 0.8, 0.95):
             comp = srv.replay(host, offsets(f * cap))
             rates.append(dict(offered_events_per_s=round(f * cap, 1), **latency_summary(comp)))
+            log(f"served at {f:.2f} x capacity: {rates[-1]}")
         out["rates"] = rates
         out["stats"] = srv.stats()
     log(f"served capacity {cap:.4g} events/s; " + ", ".join(f"{r['offered_events_per_s']:.3g}/s: p50 {r['p50_us']} us "
@@ -91,6 +95,7 @@ def served_leg(pv, synth, n_events):
     n_plain = min(n_events, 4000)
     sub = batch.select(range(n_plain))
     hp = pv.HostEvents(sub, params.max_vertices_per_event)
+    log(f"plain per-event server on {n_plain} events")
     with pv.Server(params, batch.beamline, plain_cfg) as srv:
         comp = srv.replay(hp, np.zeros(n_plain, dtype=np.int64))
         pcap = latency_summary(comp)["achieved_events_per_s"]
@@ -116,7 +121,8 @@ def main():
                     help="events timed with one launch each (plain form)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", default="", help="waves,capacity,persistent,teams_per_cu")
+    ap.add_argument("--schedule", default="",
+                    help="waves,capacity,persistent,teams_per_cu (default: chosen by pv_autotune on the batch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (HBM counter calibration)")
     ap.add_argument("--served-events", type=int, default=20000,
@@ -142,14 +148,9 @@ def main():
     batch = synth.generate(args.workload, keep_truth=False)
     log(f"generated {batch.n_events} events / {batch.n_tracks} tracks in {time.time() - t0:.1f} s")
     params = pv.pv_params_default()
-    sched = None
     if args.schedule:
         w, c, m, t = (int(v) for v in args.schedule.split(","))
-        sched = pv.pv_schedule(w, c, m, t)
         pv.pv_set_schedule(w, c, m, t)
-    s = pv.pv_get_schedule()
-    schedule = dict(waves_per_team=s.waves_per_team, track_capacity=s.track_capacity, persistent=s.persistent,
-                    teams_per_cu=s.teams_per_cu)
 
     if args.calibrate_copy_mib > 0:
         # a plain copy kernel reading and writing a known number of bytes
@@ -163,6 +164,13 @@ def main():
 
     db = pv.to_device(batch, dev)
     out = pv.alloc_outputs(db, params.max_vertices_per_event, dev)
+    tuned_us = None
+    if not args.schedule:
+        best, tuned_us = pv.pv_autotune(db, out, params, reps=5)
+        log(f"autotuned schedule {best}: {tuned_us:.1f} us per launch")
+    s = pv.pv_get_schedule()
+    schedule = dict(waves_per_team=s.waves_per_team, track_capacity=s.track_capacity, persistent=s.persistent,
+                    teams_per_cu=s.teams_per_cu, autotuned=not args.schedule)
     stream = torch.cuda.current_stream()
     L = pv.lib()
     tr, bl, ov, ot = pv._args(db, out, params)

@@ -467,6 +467,10 @@ class Server:
     def replay(self, events: HostEvents, t_offset_ns: np.ndarray) -> np.ndarray:
         n = events.batch.n_events
         offs = np.ascontiguousarray(t_offset_ns, dtype=np.int64)
+        if offs.shape != (n,):
+            raise ValueError(f"replay needs one arrival offset per event ({n}), got {offs.shape}")
+        if n and (offs.min() < 0 or np.any(np.diff(offs) < 0)):
+            raise ValueError("arrival offsets must be non-negative and non-decreasing")
         out = np.zeros(max(n, 1), dtype=COMPLETION_DTYPE)
         _check(_server_lib().pv_server_replay(self.handle, ctypes.addressof(events.requests), offs.ctypes.data, n,
                                               out.ctypes.data))
