@@ -131,7 +131,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so the "
-              f"path shards by event range across GPUs without any exchange; this build measures one GPU.",
+              f"path shards by event range across GPUs without any exchange; bench.py measures one GPU.",
               file=sys.stderr)
         sys.exit(2)
 

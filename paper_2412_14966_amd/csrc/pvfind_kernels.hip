@@ -32,11 +32,7 @@
 //             compaction of the kept vertices, final weights per track
 // Events with more tracks than a small team holds go to a second launch with
 // four-wavefront teams holding 4096 tracks.
-#include <hip/hip_runtime.h>
-#include <limits.h>
-#include <math.h>
-
-#include "pvfind_internal.h"
+#include "pvfind_device.h"
 
 namespace pvk {
 
@@ -69,311 +65,6 @@ struct __align__(16) Smem {
     unsigned long long occ;
     int ev, status, n_cl, n_live, done, n_keep;
 };
-
-constexpr int kInfoNotConv = 1 << 8;
-constexpr int kInfoFailed = 1 << 9;
-
-__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
-{
-    return (1ull << lane) - 1ull;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v, int lane)
-{
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(v, off);
-        if (lane >= off)
-            v += t;
-    }
-    return v;
-}
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v = min(v, __shfl_xor(v, off));
-    return v;
-}
-
-// Sum over aligned groups of L lanes; every lane of a group gets the same
-// bits (the pairs added are the same, addition is commutative).  Within a
-// row of 16 lanes the partners come from DPP (quad permutes, half-row and
-// row mirrors), across rows from a swizzle and a permute.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-template <int L>
-__device__ __forceinline__ float group_sum(float v)
-{
-    if (L >= 2)
-        v += dpp_f<0xB1>(v);     // quad_perm [1,0,3,2]
-    if (L >= 4)
-        v += dpp_f<0x4E>(v);     // quad_perm [2,3,0,1]
-    if (L >= 8)
-        v += dpp_f<0x141>(v);    // row_half_mirror: lane i <-> 7 - i
-    if (L >= 16)
-        v += dpp_f<0x140>(v);    // row_mirror: lane i <-> 15 - i
-    if (L >= 32)
-        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));   // xor 16
-    if (L >= 64)
-        v += __shfl_xor(v, 32);
-    return v;
-}
-
-__device__ __forceinline__ void load_track(const KArgs &A, int g, float t[8])
-{
-    t[0] = A.x[g];
-    t[1] = A.y[g];
-    t[2] = A.z[g];
-    t[3] = A.tx[g];
-    t[4] = A.ty[g];
-    t[5] = A.cxx[g];
-    t[6] = A.cxtx[g];
-    t[7] = A.ctxtx[g];
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 3.1: projection to the point of closest approach (Eq. 1, Eq. 3)
-// ---------------------------------------------------------------------------
-struct Proj {
-    float zp, sg;
-    int bin, fl;
-};
-
-__device__ __forceinline__ Proj project(float x, float y, float z, float tx, float ty, float vxx,
-                                        float vxtx, float vtxtx, const KParams &p)
-{
-    Proj r{0.0f, 0.0f, -1, 0};
-    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(tx) && isfinite(ty) && isfinite(vxx) &&
-          isfinite(vxtx) && isfinite(vtxtx))) {
-        r.fl = kTrNonfinite;
-        return r;
-    }
-    const float dtx = tx - p.btx;
-    const float dty = ty - p.bty;
-    const float dx = p.bx - x;
-    const float dy = p.by - y;
-    const float num = dtx * dx + dty * dy;
-    const float den = dtx * dtx + dty * dty;
-    if (!(den > 0.0f) || !(vxx > 0.0f))
-        return r;
-    const float zp = z + num / den;
-    const float s2 = vxx / den;
-    const float sg = sqrtf(s2);
-    r.zp = zp;
-    r.sg = sg;
-    if (!(zp >= p.z_min && zp < p.z_max))
-        return r;
-    int b = (int)floorf((zp - p.z_min) / p.dz);
-    b = min(max(b, 0), p.nb - 1);
-    r.bin = b;
-    r.fl = kTrAssoc;
-    const float smax = (b < p.gas_bin) ? p.sigma_max_gas : p.sigma_max_pp;
-    const float sw = p.u0 * sg;
-    if (s2 <= smax * smax && sw > 0.0f)
-        r.fl |= kTrHist;
-    return r;
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 3.2: kernel mass left of a bin edge, cubic cumulative, fixed point
-// ---------------------------------------------------------------------------
-// r = 1 / (u0 sigma), correctly rounded, once per track
-__device__ __forceinline__ int edge_code(float e, float zp, float r, float unit)
-{
-    float s = (e - zp) * r;
-    if (s < -1.0f)
-        s = -1.0f;
-    if (s > 1.0f)
-        s = 1.0f;
-    const float P = 0.5f + s * (0.75f - 0.25f * (s * s));
-    return (int)rintf(P * unit);
-}
-
-// Window of edges [jl, jh] whose codes are computed for a track at zp with
-// half-width sw: any superset of the kernel's support gives the same
-// integers, so the bounds may be approximate; one extra edge on each side
-// makes the end codes exactly 0 and 'full'.
-struct Window {
-    int jl, jh;   // bins jl .. jh-1 receive mass
-};
-
-__device__ __forceinline__ Window track_window(float zp, float sw, const KParams &p)
-{
-    const float fl = fmaxf(floorf((zp - sw - p.z_min) * p.inv_dz) - 1.0f, 0.0f);
-    const float fh = fminf(ceilf((zp + sw - p.z_min) * p.inv_dz) + 1.0f, (float)p.nb);
-    return Window{(int)fl, (int)fh};
-}
-
-__device__ __forceinline__ int code_at(int j, float zp, float r, const KParams &p)
-{
-    // first edge of the histogram: P = 0; last edge: P = 1
-    if (j <= 0)
-        return 0;
-    if (j >= p.nb)
-        return (int)p.unit;
-    return edge_code(p.z_min + (float)j * p.dz, zp, r, p.unit);
-}
-
-constexpr int kShortWindow = 8;   // bins per lane in the per-lane pass
-
-// per-lane pass: windows of at most kShortWindow bins, fixed trip count
-__device__ __forceinline__ void fill_short(int *hist, Window w, float zp, float r, const KParams &p)
-{
-    int prev = code_at(w.jl, zp, r, p);
-#pragma unroll
-    for (int u = 0; u < kShortWindow; ++u) {
-        const int j = w.jl + u;
-        if (j < w.jh) {
-            const int next = code_at(j + 1, zp, r, p);
-            const int d = next - prev;
-            if (d != 0)
-                atomicAdd(&hist[j], d);
-            prev = next;
-        }
-    }
-}
-
-__device__ __forceinline__ unsigned long long window_words(Window w)
-{
-    const int wl = w.jl >> 6, wh = (w.jh - 1) >> 6;
-    return (2ull << wh) - (1ull << wl);
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e].
-// Returns the number of clusters; with `write` stores them from index `first`.
-// ---------------------------------------------------------------------------
-// Bins [s, e] are read 8 at a time with independent LDS loads so that one
-// lane's serial walk pays the LDS latency once per 8 bins.
-__device__ __forceinline__ int sum_bins(const int *h, int s, int e)
-{
-    int tot = 0;
-    for (int k0 = s; k0 <= e; k0 += 8) {
-        int v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            v[u] = (k0 + u <= e) ? h[k0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            tot += v[u];
-    }
-    return tot;
-}
-
-// first index of the highest bin in [s, e]
-__device__ __forceinline__ int argmax_bins(const int *h, int s, int e)
-{
-    int im = s, best = INT_MIN;
-    for (int k0 = s; k0 <= e; k0 += 8) {
-        int v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            v[u] = (k0 + u <= e) ? h[k0 + u] : INT_MIN;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (v[u] > best) {
-                best = v[u];
-                im = k0 + u;
-            }
-    }
-    return im;
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e]
-// with bin total `tot`.  Returns the number of clusters; with `write` stores
-// them from index `first`.
-// ---------------------------------------------------------------------------
-// Without `write`, the first four split points (cluster ends) are also
-// packed into *cuts (16 bits each), their count into *nsplit and whether the
-// remainder is a cluster into *fin, so the clusters can be written without a
-// second walk.
-template <int W, int CAP>
-__device__ __forceinline__ int walk_proto(Smem<W, CAP> &S, const KParams &p, int s, int e, int tot, bool write,
-                                          int first, unsigned long long *cuts = nullptr, int *nsplit = nullptr,
-                                          int *fin = nullptr)
-{
-    const int *h = S.u.hist;
-    const bool strad = (s < p.gas_bin) && (e >= p.gas_bin);
-    const int ifix = (s < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
-    auto thr = [&](int lo, int hi) -> int {
-        if (!strad)
-            return ifix;
-        return (argmax_bins(h, lo, hi) < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
-    };
-    int count = 0;
-    auto emit = [&](int lo, int hi) {
-        if (write) {
-            const int q = first + count;
-            if (q < p.max_vertices) {
-                S.clo[q] = (short)lo;
-                S.chi[q] = (short)hi;
-            }
-        }
-        ++count;
-    };
-    int cs = s, pcs = 0, ns = 0;
-    unsigned long long cw = 0ull;
-    int up = 1, M = 0, m = 0, mj = s, pm = 0, pref = 0;
-    for (int k0 = s; k0 <= e; k0 += 8) {
-        int v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            v[u] = (k0 + u <= e) ? h[k0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u;
-            if (k > e)
-                break;
-            const int hk = v[u];
-            pref += hk;
-            if (k == s) {
-                M = hk;
-            } else if (up) {
-                if (hk > M) {
-                    M = hk;
-                } else if (hk <= M - p.dip_prom) {
-                    up = 0;
-                    m = hk;
-                    mj = k;
-                    pm = pref;
-                }
-            } else {
-                if (hk < m) {
-                    m = hk;
-                    mj = k;
-                    pm = pref;
-                } else if (hk >= m + p.dip_prom) {
-                    if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
-                        emit(cs, mj);
-                        if (ns < 4)
-                            cw |= (unsigned long long)(unsigned)mj << (16 * ns);
-                        ++ns;
-                        cs = mj + 1;
-                        pcs = pm;
-                    }
-                    up = 1;
-                    M = hk;
-                }
-            }
-        }
-    }
-    const bool last = tot - pcs >= thr(cs, e);
-    if (last)
-        emit(cs, e);
-    if (cuts) {
-        *cuts = cw;
-        *nsplit = ns;
-        *fin = last ? 1 : 0;
-    }
-    return count;
-}
 
 // Whole peak search, run by wavefront 0.  Proto-cluster runs come from
 // ballots of (bin > proto_thr) over the touched 64-bin words; they are queued
@@ -443,14 +134,14 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
                 s = S.ps[lane];
                 e = S.pe[lane];
             }
-            const int tot = has ? sum_bins(S.u.hist, s, e) : 0;
+            const int tot = has ? sum_bins(S.u.hist, 0, s, e) : 0;
             unsigned long long cw = 0ull;
             int ns = 0, fin = 0;
-            const int c = has ? walk_proto(S, p, s, e, tot, false, 0, &cw, &ns, &fin) : 0;
+            const int c = has ? walk_proto(S.u.hist, 0, S.clo, S.chi, p.max_vertices, p, s, e, tot, false, 0, &cw, &ns, &fin) : 0;
             const int incl = wave_incl_scan(c, lane);
             const int first = n_found + incl - c;
             if (has && ns > 4) {
-                walk_proto(S, p, s, e, tot, true, first);   // rare: more splits than recorded
+                walk_proto(S.u.hist, 0, S.clo, S.chi, p.max_vertices, p, s, e, tot, true, first);   // rare: more splits than recorded
             } else if (has) {
                 int lo = s, q = first;
 #pragma unroll
@@ -483,7 +174,7 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
     for (int q = lane; q < ncl; q += 64) {
         const int lo = S.clo[q], hi = S.chi[q];
         const int *h = S.u.hist;
-        const int im = argmax_bins(h, lo, hi);
+        const int im = argmax_bins(h, 0, lo, hi);
         const int Ni = h[im];
         const int Nm = (im > 0) ? h[im - 1] : 0;
         const int Np = (im + 1 < p.nb) ? h[im + 1] : 0;
@@ -497,76 +188,6 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
         S.n_cl = ncl;
         if (n_found > p.max_vertices)
             S.status |= PV_EV_VERTEX_OVERFLOW;
-    }
-}
-
-// centre of bin i, z_i of Eq. 4; the fit's frame is anchored there because
-// z_i is exact in binary32 for the usual ranges while z_seed is not
-__device__ __forceinline__ float bin_centre(int i, const KParams &p)
-{
-    return p.z_min + ((float)i + 0.5f) * p.dz;
-}
-
-__device__ __forceinline__ int lower_bound_bins(const int *pb, int n, int bin)
-{
-    int lo = 0, hi = n - 1;   // pb[n-1] >= every bin
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (pb[mid] >= bin)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
-// 3x3 covariance C = A^-1 for A = [[a, 0, -b], [0, a, -c], [-b, -c, d]] (Eq. 14).
-template <typename T>
-__device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
-{
-    const T D = a * d - b * b - c * c;
-    const T det = a * D;
-    const T r = T(1) / det;
-    out[0] = (a * d - c * c) * r;   // xx
-    out[1] = (b * c) * r;           // xy
-    out[2] = (a * d - b * b) * r;   // yy
-    out[3] = (a * b) * r;           // xz
-    out[4] = (a * c) * r;           // yz
-    out[5] = (a * a) * r;           // zz
-    return det;
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 3.5: Newton-Raphson fit of every live vertex, L lanes per vertex.
-// Each lane keeps up to kRegTracks of its vertex's tracks in registers for
-// all iterations (the rest, if any, is re-read from LDS each iteration).
-// ---------------------------------------------------------------------------
-constexpr int kRegTracks = 8;
-
-struct FitSums {
-    float s0, sx, sy, szz, gx, gy, gz, sw;
-};
-
-__device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float tx, float ty, float wt, float dx,
-                                           float dy, float dz, const KParams &p)
-{
-    // residual (Eq. 9) relative to the frame origin, chi2 (Eq. 7), Tukey weight (Eq. 17)
-    const float rx = fmaf(dz, tx, X) - dx;
-    const float ry = fmaf(dz, ty, Y) - dy;
-    const float chi2 = wt * fmaf(rx, rx, ry * ry);
-    if (chi2 < p.chi2_max) {
-        const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
-        const float w = u * u;
-        const float ww = w * wt;
-        a.sw += w;
-        a.s0 += ww;
-        a.sx = fmaf(ww, tx, a.sx);
-        a.sy = fmaf(ww, ty, a.sy);
-        a.szz = fmaf(ww, fmaf(tx, tx, ty * ty), a.szz);
-        const float px = ww * rx, py = ww * ry;
-        a.gx += px;
-        a.gy += py;
-        a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
     }
 }
 
@@ -740,18 +361,6 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int 
     }
 }
 
-// Stage boundaries for the per-stage cycle counters of the debug variant.
-struct Stamps {
-    unsigned long long t[9];
-};
-
-template <bool DEBUG>
-__device__ __forceinline__ void stamp(Stamps &st, int k)
-{
-    if (DEBUG)
-        st.t[k] = clock64();
-}
-
 // ---------------------------------------------------------------------------
 // one event
 // ---------------------------------------------------------------------------
@@ -839,7 +448,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
                     words |= window_words(w);
                     wide = (w.jh - w.jl) > kShortWindow;
                     if (!wide)
-                        fill_short(S.u.hist, w, r.zp, rinv, p);
+                        fill_short(S.u.hist, 0, w, r.zp, rinv, p);
                 }
             }
             unsigned long long wm = __ballot(wide);
@@ -1279,13 +888,35 @@ static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t 
     return err;
 }
 
+// Single-wavefront teams (pvfind_wave.hip); the events they defer (too many
+// tracks, touched histogram words or clusters) go to the large-team launch.
+template <bool DEBUG>
+static hipError_t launch_wave_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
+{
+    hipError_t err = record(ev ? ev->main_begin : nullptr, st);
+    const int mode = (s.persistent == 1 || A.n_events_dev) ? 1 : 0;
+    if (err == hipSuccess)
+        err = (hipError_t)launch_wave(A, s.track_capacity, mode, s.teams_per_cu, device_cus(), DEBUG, st);
+    if (err == hipSuccess)
+        err = record(ev ? ev->main_end : nullptr, st);
+    if (err != hipSuccess)
+        return err;
+    if (ev)
+        ev->large = true;
+    err = record(ev ? ev->large_begin : nullptr, st);
+    if (err == hipSuccess)
+        err = launch_one<kBigWaves, kBigCapacity, true, DEBUG>(A, 1, 0, st);
+    if (err == hipSuccess)
+        err = record(ev ? ev->large_end : nullptr, st);
+    return err;
+}
+
 template <bool DEBUG>
 static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     switch (s.waves_per_team * 10000 + s.track_capacity) {
-    case 10256: return launch_pair<1, 256, DEBUG>(A, s, st, ev);
-    case 10512: return launch_pair<1, 512, DEBUG>(A, s, st, ev);
-    case 11024: return launch_pair<1, 1024, DEBUG>(A, s, st, ev);
+    case 10256:
+    case 10512: return launch_wave_pair<DEBUG>(A, s, st, ev);
     case 20256: return launch_pair<2, 256, DEBUG>(A, s, st, ev);
     case 20512: return launch_pair<2, 512, DEBUG>(A, s, st, ev);
     case 21024: return launch_pair<2, 1024, DEBUG>(A, s, st, ev);

@@ -16,7 +16,9 @@ import parity
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = [dict(waves_per_team=w, track_capacity=c, persistent=m, teams_per_cu=0)
-             for w in (1, 2, 4) for c in (256, 512, 1024) for m in (1, 2)]
+             for w in (1, 2, 4) for c in (256, 512, 1024) for m in (1, 2) if (w, c) != (1, 1024)]
+WAVE = [dict(waves_per_team=1, track_capacity=c, persistent=m, teams_per_cu=0) for c in (256, 512) for m in (1, 2)]
+TEAM = dict(waves_per_team=2, track_capacity=512, persistent=1, teams_per_cu=0)
 
 
 def say(msg):
@@ -129,6 +131,36 @@ def test_events_larger_than_a_small_team_and_too_many_tracks():
     check(b, name="large events")
     lim = int(np.sort(sizes)[2])
     check(b, {"max_tracks_per_event": lim}, name=f"too many tracks (limit {lim})")
+
+
+def _spread_event(zs, per_vertex, rng):
+    return np.concatenate([_exact_event((0.0, 0.0, float(z)), per_vertex, rng) for z in zs])
+
+
+@pytest.mark.parametrize("sched", WAVE, ids=lambda s: f"c{s['track_capacity']}m{s['persistent']}")
+def test_single_wavefront_deferrals(sched):
+    """Events the single-wavefront kernel hands to the large-team launch:
+    more touched 64-bin words than its 16 pages, more clusters than its 32
+    vertex slots, more tracks than its capacity; and the largest events it
+    keeps (16 pages, 32 clusters).  Results must match the oracle and, for the
+    integer outputs, a multi-wavefront schedule."""
+    rng = np.random.default_rng(31)
+    evs = [
+        _spread_event(np.linspace(-500, 300, 20), 6, rng),     # 20 words, 20 clusters: pages
+        _spread_event(np.linspace(-560, 380, 40), 5, rng),     # 40 words, 40 clusters: both
+        _spread_event(-592.0 + 16.0 * np.arange(16), 5, rng),  # 16 words exactly, 16 clusters: kept
+        _spread_event(-590.0 + 6.0 * np.arange(32), 5, rng),   # 32 clusters in few words: kept
+        _spread_event(-590.0 + 6.0 * np.arange(34), 5, rng),   # 34 clusters: vertex slots
+        _exact_event((0.0, 0.0, 5.0), 700, rng),               # 700 tracks: capacity
+        _exact_event((0.0, 0.0, -5.0), 300, rng),              # 300 tracks: capacity 256 only
+    ]
+    b = synth.concat([synth.generate("pp_mu5_100ev", n_events=6), synth.from_tracks(evs)])
+    g, _, _ = check(b, schedule=sched, name=f"wave deferrals {sched}")
+    t = pv.run(b, schedule=TEAM, debug=True)
+    assert np.array_equal(g.track_vertex, t.track_vertex) and np.array_equal(g.n_vertices, t.n_vertices)
+    assert np.array_equal(g.hist, t.hist) and np.array_equal(g.status, t.status)
+    # fewer vertex slots than the kernel holds: overflow flagged, not deferred
+    check(b, {"max_vertices_per_event": 24}, schedule=sched, name="wave, 24 vertex slots")
 
 
 def test_vertex_overflow_and_region_parameters():
