@@ -26,7 +26,8 @@ if ROOT not in sys.path:
 
 METRIC = "events/s at mu=5 (batched vs per-event launch); p50/p99 latency in served mode"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_14966_amd", "csrc", "pvfind_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_14966_amd", "csrc", f)
+                  for f in ("pvfind_kernels.hip", "pvfind_device.h", "pvfind_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pv_find_hbm_traffic.json")
 
 
@@ -35,8 +36,11 @@ def log(msg):
 
 
 def kernel_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(n_tracks, n_events, n_vertices):
@@ -216,11 +220,14 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tf = json.load(f)
-        if tf.get("kernel_sha") == kernel_hash() and tf.get("workload") == args.workload:
+        sched_key = [schedule["waves_per_team"], schedule["track_capacity"], schedule["persistent"]]
+        if (tf.get("kernel_sha") == kernel_hash() and tf.get("workload") == args.workload
+                and tf.get("schedule") == sched_key):
             traffic = tf.get("hbm_bytes_per_launch")
+    kname = f"pv_find_kernel<{schedule['waves_per_team']}, {schedule['track_capacity']}> (main fused launch)"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "pv_find_kernel (main fused launch)", "algorithmic_bytes_per_launch": abytes,
+                "kernel": kname, "algorithmic_bytes_per_launch": abytes,
                 "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2)}
 
     # plain form: one pv_find launch per event on the same stream

@@ -156,15 +156,10 @@ typedef struct {
 
 /* How a batch is mapped onto the GPU.  Zero fields mean "library choice". */
 typedef struct {
-    int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4.
-                                          1 selects the single-wavefront kernel, whose
-                                          histogram holds 16 touched 64-bin words and
-                                          32 clusters per event; events beyond that
-                                          also go to the large-team launch            */
-    int32_t track_capacity;            /* tracks per event held by small teams: 256,
-                                          512 or 1024 (256 or 512 for one wavefront);
-                                          larger events go to a second launch with
-                                          4096-track teams                            */
+    int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4 */
+    int32_t track_capacity;            /* tracks per event held in LDS by small teams:
+                                          256, 512 or 1024; larger events go to a
+                                          second launch with 4096-track teams         */
     int32_t persistent;                /* 1: persistent grid + device work queue;
                                           2: one team per event, hardware-scheduled    */
     int32_t teams_per_cu;              /* persistent grid size per compute unit        */

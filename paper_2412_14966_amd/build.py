@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpvfind.so")
-SOURCES = [os.path.join(CSRC, "pvfind_kernels.hip"), os.path.join(CSRC, "pvfind_wave.hip"), os.path.join(CSRC, "pvfind_api.cpp"),
+SOURCES = [os.path.join(CSRC, "pvfind_kernels.hip"), os.path.join(CSRC, "pvfind_api.cpp"),
            os.path.join(CSRC, "pvfind_server.cpp")]
 ARCH = os.environ.get("PV_OFFLOAD_ARCH", "gfx950")
 

@@ -84,8 +84,6 @@ int validate_schedule(const pv_schedule &s)
         return fail(PV_EINVAL, "schedule: waves_per_team must be 1, 2 or 4 (got %d)", s.waves_per_team);
     if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024)
         return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512 or 1024 (got %d)", s.track_capacity);
-    if (s.waves_per_team == 1 && s.track_capacity == 1024)
-        return fail(PV_EINVAL, "schedule: single-wavefront teams hold 256 or 512 tracks (got 1024)");
     if (s.persistent != 1 && s.persistent != 2)
         return fail(PV_EINVAL, "schedule: persistent must be 1 or 2 (got %d)", s.persistent);
     if (s.teams_per_cu < 0 || s.teams_per_cu > 64)
@@ -468,8 +466,6 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
             for (int m : modes) {
                 if (rc != PV_OK)
                     break;
-                if (w == 1 && c == 1024)
-                    continue;   // single-wavefront teams hold at most 512 tracks
                 const pv_schedule s = {w, c, m, 0};
                 rc = find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights,
                                nullptr, &s, stream);   // warm-up, also validates the arguments

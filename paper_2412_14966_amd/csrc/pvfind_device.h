@@ -251,40 +251,55 @@ __device__ __forceinline__ int argmax_bins(const int *h, int off, int s, int e)
 
 // ---------------------------------------------------------------------------
 // Sec. 3.3: dip search and z-ordered splitting of one proto-cluster [s, e]
-// with bin total `tot`.  Returns the number of clusters; with `write` stores
-// them from index `first`.
+// with bin total `tot`, and the seed bin of every cluster (Eq. 4: its first
+// highest bin) tracked during the same walk.  h[k + off] is bin k.
+// Returns the number of clusters.  With WRITE the clusters go to clo / chi /
+// cpk from index `first` (below `cap`); otherwise the first four clusters
+// closed by a split are packed into o.rec (end bin | seed bin << 16), their
+// count into o.nsplit and the remainder's seed bin (-1: not a cluster) into
+// o.fin_peak, so that the usual case needs no second walk.
 // ---------------------------------------------------------------------------
-// Without `write`, the first four split points (cluster ends) are also
-// packed into *cuts (16 bits each), their count into *nsplit and whether the
-// remainder is a cluster into *fin, so the clusters can be written without a
-// second walk.  h[k + off] is bin k; clusters go to clo / chi below index
-// `cap`.
-__device__ __forceinline__ int walk_proto(const int *h, int off, short *clo, short *chi, int cap, const KParams &p,
-                                          int s, int e, int tot, bool write, int first,
-                                          unsigned long long *cuts = nullptr, int *nsplit = nullptr,
-                                          int *fin = nullptr)
+struct WalkOut {
+    unsigned rec[4];
+    int nsplit;
+    int fin_peak;
+};
+
+template <bool WRITE>
+__device__ __forceinline__ int walk_proto(const int *h, int off, const KParams &p, int s, int e, int tot, WalkOut &o,
+                                          short *clo, short *chi, short *cpk, int cap, int first)
 {
     const bool strad = (s < p.gas_bin) && (e >= p.gas_bin);
     const int ifix = (s < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
-    auto thr = [&](int lo, int hi) -> int {
-        if (!strad)
-            return ifix;
-        return (argmax_bins(h, off, lo, hi) < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
-    };
+    // Table 2 threshold of a cluster whose seed bin is `peak`
+    auto thr_at = [&](int peak) -> int { return (peak < p.gas_bin) ? p.min_int_gas : p.min_int_pp; };
     int count = 0;
-    auto emit = [&](int lo, int hi) {
-        if (write) {
+    auto emit = [&](int lo, int hi, int pk) {
+        if (WRITE) {
             const int q = first + count;
             if (q < cap) {
                 clo[q] = (short)lo;
                 chi[q] = (short)hi;
+                cpk[q] = (short)pk;
             }
+        } else {
+            // registers, not an indexed array (which would live in scratch)
+            const unsigned r = (unsigned)hi | ((unsigned)pk << 16);
+            if (count == 0)
+                o.rec[0] = r;
+            else if (count == 1)
+                o.rec[1] = r;
+            else if (count == 2)
+                o.rec[2] = r;
+            else if (count == 3)
+                o.rec[3] = r;
         }
         ++count;
     };
-    int cs = s, pcs = 0, ns = 0;
-    unsigned long long cw = 0ull;
+    int cs = s, pcs = 0;
     int up = 1, M = 0, m = 0, mj = s, pm = 0, pref = 0;
+    // highest bin of [cs, k] (value, first index), of (mj, k], and of [cs, mj]
+    int bM = INT_MIN, bI = s, aM = INT_MIN, aI = s, sI = s;
     for (int k0 = s; k0 <= e; k0 += 8) {
         int v[8];
 #pragma unroll
@@ -297,6 +312,14 @@ __device__ __forceinline__ int walk_proto(const int *h, int off, short *clo, sho
                 break;
             const int hk = v[u];
             pref += hk;
+            if (hk > bM) {
+                bM = hk;
+                bI = k;
+            }
+            if (hk > aM) {
+                aM = hk;
+                aI = k;
+            }
             if (k == s) {
                 M = hk;
             } else if (up) {
@@ -307,20 +330,24 @@ __device__ __forceinline__ int walk_proto(const int *h, int off, short *clo, sho
                     m = hk;
                     mj = k;
                     pm = pref;
+                    sI = bI;
+                    aM = INT_MIN;
                 }
             } else {
                 if (hk < m) {
                     m = hk;
                     mj = k;
                     pm = pref;
+                    sI = bI;
+                    aM = INT_MIN;
                 } else if (hk >= m + p.dip_prom) {
-                    if (pm - pcs >= thr(cs, mj) && tot - pm >= thr(mj + 1, e)) {
-                        emit(cs, mj);
-                        if (ns < 4)
-                            cw |= (unsigned long long)(unsigned)mj << (16 * ns);
-                        ++ns;
+                    if (pm - pcs >= (strad ? thr_at(sI) : ifix) &&
+                        tot - pm >= (strad ? thr_at(argmax_bins(h, off, mj + 1, e)) : ifix)) {
+                        emit(cs, mj, sI);
                         cs = mj + 1;
                         pcs = pm;
+                        bM = aM;
+                        bI = aI;
                     }
                     up = 1;
                     M = hk;
@@ -328,15 +355,40 @@ __device__ __forceinline__ int walk_proto(const int *h, int off, short *clo, sho
             }
         }
     }
-    const bool last = tot - pcs >= thr(cs, e);
+    const bool last = tot - pcs >= (strad ? thr_at(bI) : ifix);
     if (last)
-        emit(cs, e);
-    if (cuts) {
-        *cuts = cw;
-        *nsplit = ns;
-        *fin = last ? 1 : 0;
+        emit(cs, e, bI);
+    if (!WRITE) {
+        o.nsplit = count - (last ? 1 : 0);
+        o.fin_peak = last ? bI : -1;
     }
     return count;
+}
+
+// Write the clusters of one proto-cluster recorded by walk_proto<false>
+// from index `first`; the caller re-walks with WRITE when o.nsplit > 4.
+__device__ __forceinline__ void write_walk(const WalkOut &o, int s, int e, short *clo, short *chi, short *cpk, int cap,
+                                           int first)
+{
+    int lo = s, q = first;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < o.nsplit) {
+            const int hi = (int)(o.rec[k] & 0xFFFFu);
+            if (q < cap) {
+                clo[q] = (short)lo;
+                chi[q] = (short)hi;
+                cpk[q] = (short)(o.rec[k] >> 16);
+            }
+            ++q;
+            lo = hi + 1;
+        }
+    }
+    if (o.fin_peak >= 0 && q < cap) {
+        clo[q] = (short)lo;
+        chi[q] = (short)e;
+        cpk[q] = (short)o.fin_peak;
+    }
 }
 
 // centre of bin i, z_i of Eq. 4; the fit's frame is anchored there because

@@ -82,8 +82,4 @@ int workspace_for(void *stream, int n_events, WorkQueue **out);
 // `ev`, events are recorded around the launches.  Returns a hipError_t value.
 int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev);
 
-// Launch the single-wavefront kernel alone (capacity 256 or 512 tracks;
-// mode 1 persistent, 0 one wavefront per event; `cus` compute units).
-int launch_wave(const KArgs &args, int capacity, int mode, int teams_per_cu, int cus, bool debug, void *stream);
-
 }  // namespace pvk

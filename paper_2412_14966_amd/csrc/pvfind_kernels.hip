@@ -135,32 +135,14 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
                 e = S.pe[lane];
             }
             const int tot = has ? sum_bins(S.u.hist, 0, s, e) : 0;
-            unsigned long long cw = 0ull;
-            int ns = 0, fin = 0;
-            const int c = has ? walk_proto(S.u.hist, 0, S.clo, S.chi, p.max_vertices, p, s, e, tot, false, 0, &cw, &ns, &fin) : 0;
+            WalkOut wo{{0u, 0u, 0u, 0u}, 0, -1};
+            const int c = has ? walk_proto<false>(S.u.hist, 0, p, s, e, tot, wo, nullptr, nullptr, nullptr, 0, 0) : 0;
             const int incl = wave_incl_scan(c, lane);
             const int first = n_found + incl - c;
-            if (has && ns > 4) {
-                walk_proto(S.u.hist, 0, S.clo, S.chi, p.max_vertices, p, s, e, tot, true, first);   // rare: more splits than recorded
-            } else if (has) {
-                int lo = s, q = first;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (k < ns) {
-                        const int hi = (int)((cw >> (16 * k)) & 0xFFFFull);
-                        if (q < p.max_vertices) {
-                            S.clo[q] = (short)lo;
-                            S.chi[q] = (short)hi;
-                        }
-                        ++q;
-                        lo = hi + 1;
-                    }
-                }
-                if (fin && q < p.max_vertices) {
-                    S.clo[q] = (short)lo;
-                    S.chi[q] = (short)e;
-                }
-            }
+            if (has && wo.nsplit > 4)   // rare: more splits than recorded
+                walk_proto<true>(S.u.hist, 0, p, s, e, tot, wo, S.clo, S.chi, S.cpk, p.max_vertices, first);
+            else if (has)
+                write_walk(wo, s, e, S.clo, S.chi, S.cpk, p.max_vertices, first);
             n_found += __shfl(incl, 63);
             npend = 0;
             __builtin_amdgcn_wave_barrier();
@@ -170,18 +152,16 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
     }
 
     const int ncl = min(n_found, p.max_vertices);
-    // seeds (Eq. 4-5): first highest bin, parabola-like correction from the neighbours
+    // seeds (Eq. 4-5): first highest bin (found by the walk), correction from the neighbours
     for (int q = lane; q < ncl; q += 64) {
-        const int lo = S.clo[q], hi = S.chi[q];
         const int *h = S.u.hist;
-        const int im = argmax_bins(h, 0, lo, hi);
+        const int im = S.cpk[q];
         const int Ni = h[im];
         const int Nm = (im > 0) ? h[im - 1] : 0;
         const int Np = (im + 1 < p.nb) ? h[im + 1] : 0;
         const int den = 2 * Ni - Np - Nm;
         float delta = (den > 0) ? 0.5f * (float)(Np - Nm) / (float)den : 0.0f;
         delta = fminf(fmaxf(delta, -0.5f), 0.5f);
-        S.cpk[q] = (short)im;
         S.cd0[q] = delta * p.dz;
     }
     if (lane == 0) {
@@ -888,35 +868,13 @@ static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t 
     return err;
 }
 
-// Single-wavefront teams (pvfind_wave.hip); the events they defer (too many
-// tracks, touched histogram words or clusters) go to the large-team launch.
-template <bool DEBUG>
-static hipError_t launch_wave_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
-{
-    hipError_t err = record(ev ? ev->main_begin : nullptr, st);
-    const int mode = (s.persistent == 1 || A.n_events_dev) ? 1 : 0;
-    if (err == hipSuccess)
-        err = (hipError_t)launch_wave(A, s.track_capacity, mode, s.teams_per_cu, device_cus(), DEBUG, st);
-    if (err == hipSuccess)
-        err = record(ev ? ev->main_end : nullptr, st);
-    if (err != hipSuccess)
-        return err;
-    if (ev)
-        ev->large = true;
-    err = record(ev ? ev->large_begin : nullptr, st);
-    if (err == hipSuccess)
-        err = launch_one<kBigWaves, kBigCapacity, true, DEBUG>(A, 1, 0, st);
-    if (err == hipSuccess)
-        err = record(ev ? ev->large_end : nullptr, st);
-    return err;
-}
-
 template <bool DEBUG>
 static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     switch (s.waves_per_team * 10000 + s.track_capacity) {
-    case 10256:
-    case 10512: return launch_wave_pair<DEBUG>(A, s, st, ev);
+    case 10256: return launch_pair<1, 256, DEBUG>(A, s, st, ev);
+    case 10512: return launch_pair<1, 512, DEBUG>(A, s, st, ev);
+    case 11024: return launch_pair<1, 1024, DEBUG>(A, s, st, ev);
     case 20256: return launch_pair<2, 256, DEBUG>(A, s, st, ev);
     case 20512: return launch_pair<2, 512, DEBUG>(A, s, st, ev);
     case 21024: return launch_pair<2, 1024, DEBUG>(A, s, st, ev);
