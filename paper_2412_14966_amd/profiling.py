@@ -1,15 +1,16 @@
 """Summaries of rocprofv3 CSV output for the committed profile records.
 
 ``python -m paper_2412_14966_amd.profiling trace DIR``
-    per-kernel call count and average / min / max duration from the
-    ``*_kernel_stats.csv`` (or ``*_kernel_trace.csv``) files under DIR.
+    per-(kernel, grid size) call count and average / min / max duration from
+    the ``*_kernel_trace.csv`` files under DIR.
 ``python -m paper_2412_14966_amd.profiling counters DIR COUNTER``
-    per-kernel mean value of one PMC counter per dispatch from the
+    per-(kernel, grid size) value of one PMC counter per dispatch from the
     ``*_counter_collection.csv`` files under DIR.
 ``python -m paper_2412_14966_amd.profiling traffic FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME``
     HBM bytes per launch of kernel NAME from FETCH_SIZE and WRITE_SIZE
-    (KiB per dispatch), each scaled by the factor that makes a plain copy of
-    M MiB read and write M MiB; prints the record that bench.py reads.
+    (KiB per dispatch, largest-grid launches of NAME), each scaled by the factor
+    that makes the largest dispatch of a plain copy kernel read and write M MiB;
+    prints the record that bench.py reads.
 
 Only text parsing: nothing here touches the GPU.
 """
@@ -46,40 +47,42 @@ def short_name(name: str) -> str:
     return name.split("(")[0].strip()
 
 
-def kernel_times(root: str) -> Dict[str, dict]:
-    """Per-kernel {calls, avg_ns, min_ns, max_ns} from a kernel trace."""
-    out: Dict[str, dict] = {}
-    trace = _rows(root, "kernel_trace.csv")
-    if trace:
-        durs = defaultdict(list)
-        for r in trace:
-            durs[short_name(_col(r, "Kernel_Name"))].append(int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp")))
-        for k, d in durs.items():
-            out[k] = dict(calls=len(d), avg_ns=sum(d) / len(d), min_ns=min(d), max_ns=max(d))
-        return out
-    for r in _rows(root, "kernel_stats.csv"):
-        out[short_name(_col(r, "Name"))] = dict(calls=int(_col(r, "Calls")), avg_ns=float(_col(r, "AverageNs")),
-                                                min_ns=float(_col(r, "MinNs")), max_ns=float(_col(r, "MaxNs")))
-    return out
+def _grid(row: dict) -> int:
+    for names in (("Grid_Size",), ("Grid_Size_X",)):
+        try:
+            return int(_col(row, *names))
+        except KeyError:
+            pass
+    return 0
 
 
-def counter_means(root: str, counter: str) -> Dict[str, dict]:
-    """Per-kernel mean of `counter` per dispatch (summed over the counter's
-    instances within a dispatch)."""
+def kernel_times(root: str) -> Dict[tuple, dict]:
+    """Per-(kernel, grid size) {calls, avg_ns, min_ns, max_ns} from a kernel trace."""
+    durs = defaultdict(list)
+    for r in _rows(root, "kernel_trace.csv"):
+        key = (short_name(_col(r, "Kernel_Name")), _grid(r))
+        durs[key].append(int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp")))
+    return {k: dict(calls=len(d), avg_ns=sum(d) / len(d), min_ns=min(d), max_ns=max(d)) for k, d in durs.items()}
+
+
+def counter_values(root: str, counter: str) -> Dict[tuple, List[float]]:
+    """Per-(kernel, grid size) list of `counter` per dispatch (summed over the
+    counter's instances within a dispatch)."""
     per = defaultdict(lambda: defaultdict(float))
     for r in _rows(root, "counter_collection.csv"):
         if _col(r, "Counter_Name") != counter:
             continue
         disp = _col(r, "Dispatch_Id", "Correlation_Id")
-        per[short_name(_col(r, "Kernel_Name"))][disp] += float(_col(r, "Counter_Value"))
-    return {k: dict(dispatches=len(v), mean=sum(v.values()) / len(v)) for k, v in per.items()}
+        per[(short_name(_col(r, "Kernel_Name")), _grid(r))][disp] += float(_col(r, "Counter_Value"))
+    return {k: list(v.values()) for k, v in per.items()}
 
 
-def _pick(d: Dict[str, dict], key: str) -> str:
-    hits = [k for k in d if key in k]
+def _largest(d: Dict[tuple, object], key: str) -> tuple:
+    """(kernel, grid) entry of the kernel matching `key` with the largest grid."""
+    hits = [k for k in d if key in k[0]]
     if not hits:
-        raise SystemExit(f"no kernel matching {key!r}: {sorted(d)}")
-    return hits[0]
+        raise SystemExit(f"no kernel matching {key!r}: {sorted(set(k[0] for k in d))}")
+    return max(hits, key=lambda k: k[1])
 
 
 def main(argv=None) -> int:
@@ -98,31 +101,36 @@ def main(argv=None) -> int:
     h.add_argument("--kernel", required=True, help="substring naming the profiled kernel")
     h.add_argument("--workload", default="")
     h.add_argument("--kernel-sha", default="")
+    h.add_argument("--schedule", type=lambda t: [int(x) for x in t.split(",")], default=None,
+                   help="waves,capacity,persistent of the profiled launches")
     a = ap.parse_args(argv)
 
     if a.cmd == "trace":
-        print("| kernel | calls | avg us | min us | max us |\n|---|---|---|---|---|")
-        for k, v in sorted(kernel_times(a.dir).items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
-            print(f"| `{k}` | {v['calls']} | {v['avg_ns'] / 1e3:.1f} | {v['min_ns'] / 1e3:.1f} | {v['max_ns'] / 1e3:.1f} |")
+        print("| kernel | grid (work-items) | calls | avg us | min us | max us |\n|---|---|---|---|---|---|")
+        for (k, g), v in sorted(kernel_times(a.dir).items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+            print(f"| `{k}` | {g} | {v['calls']} | {v['avg_ns'] / 1e3:.2f} | {v['min_ns'] / 1e3:.2f} | "
+                  f"{v['max_ns'] / 1e3:.2f} |")
         return 0
     if a.cmd == "counters":
-        print(f"| kernel | dispatches | mean {a.counter} per dispatch |\n|---|---|---|")
-        for k, v in sorted(counter_means(a.dir, a.counter).items()):
-            print(f"| `{k}` | {v['dispatches']} | {v['mean']:.6g} |")
+        print(f"| kernel | grid (work-items) | dispatches | mean {a.counter} | min | max |\n|---|---|---|---|---|---|")
+        for (k, g), v in sorted(counter_values(a.dir, a.counter).items()):
+            print(f"| `{k}` | {g} | {len(v)} | {sum(v) / len(v):.6g} | {min(v):.6g} | {max(v):.6g} |")
         return 0
-    fetch = counter_means(a.fetch_dir, "FETCH_SIZE")
-    write = counter_means(a.write_dir, "WRITE_SIZE")
+    fetch = counter_values(a.fetch_dir, "FETCH_SIZE")
+    write = counter_values(a.write_dir, "WRITE_SIZE")
     copy_kib = a.copy_mib * 1024.0
-    kf, kw = _pick(fetch, a.copy_kernel), _pick(write, a.copy_kernel)
-    f_scale = copy_kib / fetch[kf]["mean"]
-    w_scale = copy_kib / write[kw]["mean"]
-    mf, mw = _pick(fetch, a.kernel), _pick(write, a.kernel)
-    fetch_b = fetch[mf]["mean"] * f_scale * 1024.0
-    write_b = write[mw]["mean"] * w_scale * 1024.0
-    rec = dict(workload=a.workload, kernel_sha=a.kernel_sha, kernel=mf,
-               fetch_kib_raw=fetch[mf]["mean"], write_kib_raw=write[mw]["mean"],
-               copy_kernel=kf, copy_fetch_kib_raw=fetch[kf]["mean"], copy_write_kib_raw=write[kw]["mean"],
-               fetch_scale=f_scale, write_scale=w_scale, hbm_bytes_per_launch=fetch_b + write_b)
+    # the calibration copy is the largest dispatch of the copy kernel
+    cf = max(max(v) for k, v in fetch.items() if a.copy_kernel in k[0])
+    cw = max(max(v) for k, v in write.items() if a.copy_kernel in k[0])
+    f_scale, w_scale = copy_kib / cf, copy_kib / cw
+    kf, kw = _largest(fetch, a.kernel), _largest(write, a.kernel)
+    mf = sum(fetch[kf]) / len(fetch[kf])
+    mw = sum(write[kw]) / len(write[kw])
+    rec = dict(workload=a.workload, kernel_sha=a.kernel_sha, schedule=a.schedule, kernel=kf[0], grid=kf[1],
+               dispatches=len(fetch[kf]), fetch_kib_raw=mf, write_kib_raw=mw,
+               copy_mib=a.copy_mib, copy_fetch_kib_raw=cf, copy_write_kib_raw=cw,
+               fetch_scale=f_scale, write_scale=w_scale,
+               hbm_bytes_per_launch=(mf * f_scale + mw * w_scale) * 1024.0)
     json.dump(rec, sys.stdout, indent=1)
     print()
     return 0
