@@ -68,22 +68,51 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // group_sum<L> for a wavefront-uniform L (one copy of the caller's code
-// serves every group size)
+// serves every group size).  Every butterfly level runs and a select keeps
+// the levels below L, so no branch depends on L.
 __device__ __forceinline__ float group_sum_rt(float v, int L)
 {
-    if (L >= 2)
-        v += dpp_f<0xB1>(v);
-    if (L >= 4)
-        v += dpp_f<0x4E>(v);
-    if (L >= 8)
-        v += dpp_f<0x141>(v);
-    if (L >= 16)
-        v += dpp_f<0x140>(v);
-    if (L >= 32)
-        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
-    if (L >= 64)
-        v += __shfl_xor(v, 32);
+    float t = dpp_f<0xB1>(v);
+    v = (L >= 2) ? v + t : v;
+    t = dpp_f<0x4E>(v);
+    v = (L >= 4) ? v + t : v;
+    t = dpp_f<0x141>(v);
+    v = (L >= 8) ? v + t : v;
+    t = dpp_f<0x140>(v);
+    v = (L >= 16) ? v + t : v;
+    t = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    v = (L >= 32) ? v + t : v;
+    t = __shfl_xor(v, 32);
+    v = (L >= 64) ? v + t : v;
     return v;
+}
+
+// The eight sums of one Newton step at once, for a wavefront-uniform L: the
+// in-row levels are branch-free; the two cross-row levels, which go through
+// the LDS crossbar, run only for groups of 32 and 64 lanes.
+__device__ __forceinline__ void group_sum8_rt(float v[8], int L)
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float t = dpp_f<0xB1>(v[k]);
+        v[k] = (L >= 2) ? v[k] + t : v[k];
+        t = dpp_f<0x4E>(v[k]);
+        v[k] = (L >= 4) ? v[k] + t : v[k];
+        t = dpp_f<0x141>(v[k]);
+        v[k] = (L >= 8) ? v[k] + t : v[k];
+        t = dpp_f<0x140>(v[k]);
+        v[k] = (L >= 16) ? v[k] + t : v[k];
+    }
+    if (L >= 32) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            v[k] += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v[k]), 0x401F));
+    }
+    if (L >= 64) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            v[k] += __shfl_xor(v[k], 32);
+    }
 }
 
 // Track indices are non-negative 32-bit values: unsigned indexing lets the

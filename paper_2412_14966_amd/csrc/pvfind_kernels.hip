@@ -36,6 +36,15 @@
 
 namespace pvk {
 
+// Fit state of the live vertices: position relative to the frame, the last
+// normal matrix (a, b, c, d as in Eq. 14) and n_iter | not_converged << 8 |
+// failed << 9.
+struct VertexFit {
+    float dx[kMaxVertices], dy[kMaxVertices], dz[kMaxVertices];
+    float a[kMaxVertices], b[kMaxVertices], c[kMaxVertices], d[kMaxVertices];
+    int info[kMaxVertices];
+};
+
 template <int W, int CAP>
 struct __align__(16) Smem {
     union {
@@ -56,10 +65,10 @@ struct __align__(16) Smem {
     int pb[kMaxVertices];    // last bin owned by live slot k
     int cnt[kMaxVertices];   // tracks owned by live slot k
     int base[kMaxVertices];  // first gathered slot of live slot k
-    int wrun[W][kMaxVertices];
-    float vdx[kMaxVertices], vdy[kMaxVertices], vdz[kMaxVertices];
-    float va[kMaxVertices], vb[kMaxVertices], vc[kMaxVertices], vd[kMaxVertices];
-    int vinfo[kMaxVertices]; // n_iter | not_converged << 8 | failed << 9
+    union {
+        int wrun[W][kMaxVertices];   // gather: running slot per wavefront and live slot
+        VertexFit vf;                // fit onwards
+    };
     int vout[kMaxVertices];
     short ps[64], pe[64];    // pending proto-clusters
     unsigned long long occ;
@@ -171,13 +180,15 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
     }
 }
 
-template <int W, int CAP, int L>
-__device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, int nl)
+// L = 1 << lg lanes per vertex, wavefront-uniform (scalar): one copy of the
+// code serves every group size.
+template <int W, int CAP>
+__device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, int nl, int L, int lg)
 {
     constexpr int NT = 64 * W;
-    constexpr int G = NT / L;
+    const int G = NT >> lg;
     const int tid = threadIdx.x;
-    const int gid = tid / L, gl = tid % L;
+    const int gid = tid >> lg, gl = tid & (L - 1);
     for (int k0 = 0; k0 < nl; k0 += G) {
         const int k = k0 + gid;
         const bool has = k < nl;
@@ -218,9 +229,9 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, 
                         accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
                 }
             }
-            const float s0 = group_sum<L>(a.s0), sx = group_sum<L>(a.sx), sy = group_sum<L>(a.sy);
-            const float szz = group_sum<L>(a.szz), gx = group_sum<L>(a.gx), gy = group_sum<L>(a.gy);
-            const float gz = group_sum<L>(a.gz), sw = group_sum<L>(a.sw);
+            float r[8] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz, a.sw};
+            group_sum8_rt(r, L);
+            const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6], sw = r[7];
             if (active) {
                 // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
                 // det(A) = s0 * D, singular when det <= sing_ratio * s0 * s0 * szz
@@ -251,34 +262,34 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, 
             }
         }
         if (has && gl == 0) {
-            S.vdx[k] = dx;
-            S.vdy[k] = dy;
-            S.vdz[k] = dz;
-            S.va[k] = la;
-            S.vb[k] = lb;
-            S.vc[k] = lc;
-            S.vd[k] = ld;
-            S.vinfo[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
+            S.vf.dx[k] = dx;
+            S.vf.dy[k] = dy;
+            S.vf.dz[k] = dz;
+            S.vf.a[k] = la;
+            S.vf.b[k] = lb;
+            S.vf.c[k] = lc;
+            S.vf.d[k] = ld;
+            S.vf.info[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
         }
     }
 }
 
 // Final Tukey weights at the fitted position, per-track outputs, chi2 and
 // ndof (2 sum w - 3), covariance (Eq. 14) and the vertex record.
-template <int W, int CAP, int L>
-__device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int e, int a, int nl)
+template <int W, int CAP>
+__device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int e, int a, int nl, int L, int lg)
 {
     constexpr int NT = 64 * W;
-    constexpr int G = NT / L;
+    const int G = NT >> lg;
     const KParams &p = A.p;
     const int tid = threadIdx.x;
-    const int gid = tid / L, gl = tid % L;
+    const int gid = tid >> lg, gl = tid & (L - 1);
     for (int k0 = 0; k0 < nl; k0 += G) {
         const int k = k0 + gid;
         const bool has = k < nl;
         const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
         const int vo = has ? S.vout[k] : -1;
-        const float dx = has ? S.vdx[k] : 0.0f, dy = has ? S.vdy[k] : 0.0f, dz = has ? S.vdz[k] : 0.0f;
+        const float dx = has ? S.vf.dx[k] : 0.0f, dy = has ? S.vf.dy[k] : 0.0f, dz = has ? S.vf.dz[k] : 0.0f;
         float schi = 0.0f, sw = 0.0f;
         for (int t = gl; t < ck; t += L) {
             const int sl = beg + t;
@@ -299,12 +310,12 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int 
             A.trk_vtx[g] = vo;
             A.trk_w[g] = (vo >= 0) ? w : 0.0f;
         }
-        schi = group_sum<L>(schi);
-        sw = group_sum<L>(sw);
+        schi = group_sum_rt(schi, L);
+        sw = group_sum_rt(sw, L);
         if (has && gl == 0 && vo >= 0) {
             const int cq = S.live[k];
             const float zr = bin_centre(S.cpk[cq], p);
-            const float la = S.va[k], lb = S.vb[k], lc = S.vc[k], ld = S.vd[k];
+            const float la = S.vf.a[k], lb = S.vf.b[k], lc = S.vf.c[k], ld = S.vf.d[k];
             float cf[6];
             const float det = inverse_a<float>(la, lb, lc, ld, cf);
             // 1-norm condition number of A
@@ -312,7 +323,7 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int 
             const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
                                          fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
                                    fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
-            int flags = (S.vinfo[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
+            int flags = (S.vf.info[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
             if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
                 double cd[6];
                 inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
@@ -333,7 +344,7 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int 
             v.bin_lo = S.clo[cq];
             v.bin_hi = S.chi[cq];
             v.peak_bin = S.cpk[cq];
-            v.n_iter = (uint8_t)(S.vinfo[k] & 0xFF);
+            v.n_iter = (uint8_t)(S.vf.info[k] & 0xFF);
             v.flags = (uint8_t)flags;
             v.reserved = 0;
             A.vout[(size_t)e * p.max_vertices + vo] = v;
@@ -664,21 +675,15 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
 
     // fit (Sec. 3.5): L lanes per vertex, L the largest power of two with
     // L * vertices <= lanes of the team
-    int L = 64;
+    int lg = 6;
     {
         const int target = NT / max(nl, 1);
-        while (L > 1 && L > target)
-            L >>= 1;
+        while (lg > 0 && (1 << lg) > target)
+            --lg;
     }
-    switch (L) {
-    case 1: fit_vertices<W, CAP, 1>(S, p, nl); break;
-    case 2: fit_vertices<W, CAP, 2>(S, p, nl); break;
-    case 4: fit_vertices<W, CAP, 4>(S, p, nl); break;
-    case 8: fit_vertices<W, CAP, 8>(S, p, nl); break;
-    case 16: fit_vertices<W, CAP, 16>(S, p, nl); break;
-    case 32: fit_vertices<W, CAP, 32>(S, p, nl); break;
-    default: fit_vertices<W, CAP, 64>(S, p, nl); break;
-    }
+    lg = __builtin_amdgcn_readfirstlane(lg);   // the same on every lane: keep it scalar
+    const int L = 1 << lg;
+    fit_vertices<W, CAP>(S, p, nl, L, lg);
     __syncthreads();
     stamp<DEBUG>(ts, 6);
 
@@ -691,12 +696,12 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             if (k < nl) {
                 const int cq = S.live[k];
                 const bool gas = S.cpk[cq] < p.gas_bin;
-                keep = !(S.vinfo[k] & kInfoFailed) && S.cnt[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
+                keep = !(S.vf.info[k] & kInfoFailed) && S.cnt[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
                 if (keep && !gas) {
                     const float zr = bin_centre(S.cpk[cq], p);
-                    const float zv = zr + S.vdz[k];
-                    const float xv = (p.bx + p.btx * zr) + S.vdx[k];
-                    const float yv = (p.by + p.bty * zr) + S.vdy[k];
+                    const float zv = zr + S.vf.dz[k];
+                    const float xv = (p.bx + p.btx * zr) + S.vf.dx[k];
+                    const float yv = (p.by + p.bty * zr) + S.vf.dy[k];
                     const float rx = xv - (p.bx + p.btx * zv);
                     const float ry = yv - (p.by + p.bty * zv);
                     keep = fmaf(rx, rx, ry * ry) <= p.max_rho2_pp;
@@ -714,15 +719,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     stamp<DEBUG>(ts, 7);
 
     // final weights, vertex records
-    switch (L) {
-    case 1: final_pass<W, CAP, 1>(S, A, e, a, nl); break;
-    case 2: final_pass<W, CAP, 2>(S, A, e, a, nl); break;
-    case 4: final_pass<W, CAP, 4>(S, A, e, a, nl); break;
-    case 8: final_pass<W, CAP, 8>(S, A, e, a, nl); break;
-    case 16: final_pass<W, CAP, 16>(S, A, e, a, nl); break;
-    case 32: final_pass<W, CAP, 32>(S, A, e, a, nl); break;
-    default: final_pass<W, CAP, 64>(S, A, e, a, nl); break;
-    }
+    final_pass<W, CAP>(S, A, e, a, nl, L, lg);
     if (tid == 0) {
         A.nv_out[e] = S.n_keep;
         A.status_out[e] = S.status;
