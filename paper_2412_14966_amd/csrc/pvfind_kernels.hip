@@ -741,6 +741,11 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
     __shared__ Smem<W, CAP> S;
     const int tid = threadIdx.x;
     const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
+    // Nothing deferred: the large-team counters are all zero and stay so; leave
+    // without touching them (n_big is not written while this grid runs, so
+    // every workgroup sees the same value).
+    if (BIG && __hip_atomic_load(&A.wq->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        return;
     bool first = true;
     for (;;) {
         if (tid == 0) {

@@ -37,22 +37,33 @@ struct Request {
 
 enum class SlotState { Free, Open, Sealed, InFlight };
 
+// Each slot keeps its buffers in a few contiguous blocks so that a batch
+// moves with five copies: the eight track columns (one 2-D copy of rows of
+// cap_tracks floats), offsets and event count, vertex counts and status (one
+// 2-D copy), vertex records, and per-track vertex ids and weights (one 2-D
+// copy).
 struct Slot {
     int id = 0;
     hipStream_t stream = nullptr;
     SlotState state = SlotState::Free;
     // device
+    float *d_in = nullptr;          // 8 columns of cap_tracks floats, then cap_events + 2 ints
     float *d_trk[8] = {};
-    int32_t *d_offsets = nullptr;   // cap_events + 1
+    int32_t *d_offsets = nullptr;   // cap_events + 1 offsets, then the event count
     int32_t *d_nev = nullptr;
     pv_vertex *d_vtx = nullptr;
-    int32_t *d_nv = nullptr, *d_status = nullptr, *d_tv = nullptr;
+    int32_t *d_ns = nullptr;        // vertex counts, then status: 2 rows of cap_events
+    int32_t *d_nv = nullptr, *d_status = nullptr;
+    int32_t *d_tout = nullptr;      // vertex ids, then weights: 2 rows of cap_tracks
+    int32_t *d_tv = nullptr;
     float *d_tw = nullptr;
-    // pinned host
+    // pinned host, same layouts
+    float *h_in = nullptr;
     float *h_trk[8] = {};
-    int32_t *h_offsets = nullptr;   // cap_events + 2: offsets, then the event count
+    int32_t *h_offsets = nullptr;
     pv_vertex *h_vtx = nullptr;
-    int32_t *h_nv = nullptr, *h_status = nullptr, *h_tv = nullptr;
+    int32_t *h_ns = nullptr, *h_nv = nullptr, *h_status = nullptr;
+    int32_t *h_tout = nullptr, *h_tv = nullptr;
     float *h_tw = nullptr;
     pvk::WorkQueue *wq = nullptr;   // this slot's own queue counters (baked into its graph)
     hipGraphExec_t graph = nullptr;
@@ -90,18 +101,10 @@ namespace {
 
 void free_slot(Slot &s)
 {
-    for (int k = 0; k < 8; ++k) {
-        if (s.d_trk[k])
-            (void)hipFree(s.d_trk[k]);
-        if (s.h_trk[k])
-            (void)hipHostFree(s.h_trk[k]);
-    }
-    for (void *p : {(void *)s.d_offsets, (void *)s.d_nev, (void *)s.d_vtx, (void *)s.d_nv, (void *)s.d_status,
-                    (void *)s.d_tv, (void *)s.d_tw, (void *)s.wq})
+    for (void *p : {(void *)s.d_in, (void *)s.d_vtx, (void *)s.d_ns, (void *)s.d_tout, (void *)s.wq})
         if (p)
             (void)hipFree(p);
-    for (void *p : {(void *)s.h_offsets, (void *)s.h_vtx, (void *)s.h_nv, (void *)s.h_status, (void *)s.h_tv,
-                    (void *)s.h_tw})
+    for (void *p : {(void *)s.h_in, (void *)s.h_vtx, (void *)s.h_ns, (void *)s.h_tout})
         if (p)
             (void)hipHostFree(p);
     if (s.graph)
@@ -161,40 +164,39 @@ int init_slot(pv_server &s, Slot &sl)
 {
     const int T = s.cfg.max_tracks_per_batch, E = s.cfg.max_events_per_batch;
     const int mv = s.params.max_vertices_per_event;
-    int rc = PV_OK;
-    for (int k = 0; k < 8 && rc == PV_OK; ++k) {
-        rc = dev_alloc(&sl.d_trk[k], T);
-        if (rc == PV_OK)
-            rc = host_alloc(&sl.h_trk[k], T);
-    }
+    const size_t in_floats = 8 * (size_t)T + (size_t)E + 2;   // int32 and float are both 4 bytes
+    int rc = dev_alloc(&sl.d_in, in_floats);
     if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_offsets, (size_t)E + 1);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_nev, 1);
+        rc = host_alloc(&sl.h_in, in_floats);
     if (rc == PV_OK)
         rc = dev_alloc(&sl.d_vtx, (size_t)E * mv);
     if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_nv, E);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_status, E);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_tv, T);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_tw, T);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_offsets, (size_t)E + 2);
-    if (rc == PV_OK)
         rc = host_alloc(&sl.h_vtx, (size_t)E * mv);
     if (rc == PV_OK)
-        rc = host_alloc(&sl.h_nv, E);
+        rc = dev_alloc(&sl.d_ns, 2 * (size_t)E);
     if (rc == PV_OK)
-        rc = host_alloc(&sl.h_status, E);
+        rc = host_alloc(&sl.h_ns, 2 * (size_t)E);
     if (rc == PV_OK)
-        rc = host_alloc(&sl.h_tv, T);
+        rc = dev_alloc(&sl.d_tout, 2 * (size_t)T);
     if (rc == PV_OK)
-        rc = host_alloc(&sl.h_tw, T);
+        rc = host_alloc(&sl.h_tout, 2 * (size_t)T);
     if (rc != PV_OK)
         return rc;
+    for (int k = 0; k < 8; ++k) {
+        sl.d_trk[k] = sl.d_in + (size_t)k * T;
+        sl.h_trk[k] = sl.h_in + (size_t)k * T;
+    }
+    sl.d_offsets = reinterpret_cast<int32_t *>(sl.d_in + 8 * (size_t)T);
+    sl.h_offsets = reinterpret_cast<int32_t *>(sl.h_in + 8 * (size_t)T);
+    sl.d_nev = sl.d_offsets + E + 1;
+    sl.d_nv = sl.d_ns;
+    sl.d_status = sl.d_ns + E;
+    sl.h_nv = sl.h_ns;
+    sl.h_status = sl.h_ns + E;
+    sl.d_tv = sl.d_tout;
+    sl.d_tw = reinterpret_cast<float *>(sl.d_tout + T);
+    sl.h_tv = sl.h_tout;
+    sl.h_tw = reinterpret_cast<float *>(sl.h_tout + T);
     const size_t wq_bytes = sizeof(pvk::WorkQueue) + sizeof(int32_t) * (size_t)E;
     hipError_t err = hipMalloc((void **)&sl.wq, wq_bytes);
     if (err != hipSuccess)
@@ -235,17 +237,15 @@ int init_slot(pv_server &s, Slot &sl)
 int dispatch(pv_server &s, Slot &sl)
 {
     const int E = sl.n_events, T = sl.n_tracks;
+    const size_t capE = (size_t)s.cfg.max_events_per_batch, capT = (size_t)s.cfg.max_tracks_per_batch;
     hipStream_t st = sl.stream;
-    sl.h_offsets[s.cfg.max_events_per_batch + 1] = E;
+    sl.h_offsets[capE + 1] = E;
     hipError_t err = hipSuccess;
-    for (int k = 0; k < 8 && err == hipSuccess; ++k)
-        err = hipMemcpyAsync(sl.d_trk[k], sl.h_trk[k], sizeof(float) * (size_t)T, hipMemcpyHostToDevice, st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.d_offsets, sl.h_offsets, sizeof(int32_t) * (size_t)(E + 1), hipMemcpyHostToDevice,
-                             st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.d_nev, sl.h_offsets + s.cfg.max_events_per_batch + 1, sizeof(int32_t),
-                             hipMemcpyHostToDevice, st);
+    if (T > 0)   // the eight columns: 8 rows of T floats at a pitch of capT floats
+        err = hipMemcpy2DAsync(sl.d_in, capT * sizeof(float), sl.h_in, capT * sizeof(float),
+                               (size_t)T * sizeof(float), 8, hipMemcpyHostToDevice, st);
+    if (err == hipSuccess)   // offsets and, at capE + 1, the event count
+        err = hipMemcpyAsync(sl.d_offsets, sl.h_offsets, sizeof(int32_t) * (capE + 2), hipMemcpyHostToDevice, st);
     if (err != hipSuccess)
         return pvk::set_error(PV_EHIP, "server copy-in: %s", hipGetErrorString(err));
     if (sl.graph) {
@@ -259,15 +259,14 @@ int dispatch(pv_server &s, Slot &sl)
             return pvk::set_error(PV_EHIP, "server launch: %s", hipGetErrorString((hipError_t)lerr));
     }
     const size_t mv = (size_t)s.params.max_vertices_per_event;
-    err = hipMemcpyAsync(sl.h_nv, sl.d_nv, sizeof(int32_t) * (size_t)E, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_status, sl.d_status, sizeof(int32_t) * (size_t)E, hipMemcpyDeviceToHost, st);
+    // vertex counts and status: 2 rows of E ints at a pitch of capE
+    err = hipMemcpy2DAsync(sl.h_ns, capE * sizeof(int32_t), sl.d_ns, capE * sizeof(int32_t),
+                           (size_t)E * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess)
         err = hipMemcpyAsync(sl.h_vtx, sl.d_vtx, sizeof(pv_vertex) * mv * (size_t)E, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_tv, sl.d_tv, sizeof(int32_t) * (size_t)T, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_tw, sl.d_tw, sizeof(float) * (size_t)T, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess && T > 0)   // vertex ids and weights: 2 rows of T at a pitch of capT
+        err = hipMemcpy2DAsync(sl.h_tout, capT * sizeof(int32_t), sl.d_tout, capT * sizeof(int32_t),
+                               (size_t)T * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess)
         err = hipEventRecord(sl.done, st);
     if (err != hipSuccess)
@@ -314,53 +313,74 @@ void worker_main(pv_server *sp)
     pv_server &s = *sp;
     (void)hipSetDevice(s.device);
     std::vector<pv_completion> done;
+    std::vector<int> finished;
+    // s.inflight is only touched by this thread; the lock guards the slot
+    // states, the open / sealed queues and the completion list, which the
+    // callers share.  No HIP call is made with the lock held.
     std::unique_lock<std::mutex> lk(s.mu);
     while (!s.stop) {
-        // completions: results are scattered without the lock (the slot
-        // belongs to the worker until it is marked free)
-        for (size_t i = 0; i < s.inflight.size();) {
-            const int id = s.inflight[i];
-            Slot &sl = s.slots[id];
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipErrorNotReady) {
-                ++i;
-                continue;
-            }
-            if (q != hipSuccess && s.worker_error == PV_OK)
-                s.worker_error = pvk::set_error(PV_EHIP, "server batch: %s", hipGetErrorString(q));
-            s.inflight.erase(s.inflight.begin() + (long)i);
+        // completions
+        if (!s.inflight.empty()) {
             lk.unlock();
+            finished.clear();
+            for (size_t i = 0; i < s.inflight.size();) {
+                const int id = s.inflight[i];
+                const hipError_t q = hipEventQuery(s.slots[id].done);
+                if (q == hipErrorNotReady) {
+                    ++i;
+                    continue;
+                }
+                if (q != hipSuccess) {
+                    std::lock_guard<std::mutex> g(s.mu);
+                    if (s.worker_error == PV_OK)
+                        s.worker_error = pvk::set_error(PV_EHIP, "server batch: %s", hipGetErrorString(q));
+                }
+                s.inflight.erase(s.inflight.begin() + (long)i);
+                finished.push_back(id);
+            }
             done.clear();
-            complete(s, sl, done);
+            for (int id : finished)
+                complete(s, s.slots[id], done);
             lk.lock();
             for (const auto &c : done)
                 s.completed.push_back(c);
             s.n_completed += (int64_t)done.size();
-            sl.state = SlotState::Free;
-            sl.n_events = sl.n_tracks = 0;
-            sl.reqs.clear();
-            s.cv_done.notify_all();
+            for (int id : finished) {
+                Slot &sl = s.slots[id];
+                sl.state = SlotState::Free;
+                sl.n_events = sl.n_tracks = 0;
+                sl.reqs.clear();
+            }
+            if (!finished.empty())
+                s.cv_done.notify_all();
         }
-        // continuous batching: seal the open batch when a stream is free or it waited long enough
+        // continuous batching: a batch is sealed when it is full, or when a
+        // stream is free and either the GPU is idle or its oldest event has
+        // waited max_wait_us.  While every stream is busy the open batch keeps
+        // growing, so batches grow with the load.
         if (s.open >= 0) {
             const Slot &o = s.slots[s.open];
-            const bool stream_free = (int)(s.inflight.size() + s.sealed.size()) < s.cfg.n_streams;
+            const int busy = (int)(s.inflight.size() + s.sealed.size());
+            const bool stream_free = busy < s.cfg.n_streams;
+            const bool idle = busy == 0;
             const bool waited = now_ns() - o.t_oldest >= (int64_t)s.cfg.max_wait_us * 1000;
-            if (o.n_events > 0 && (stream_free || waited || o.n_events >= s.cfg.max_events_per_batch))
+            if (o.n_events > 0 && (o.n_events >= s.cfg.max_events_per_batch || (stream_free && (idle || waited))))
                 seal_open(s);
         }
-        // launches, oldest batch first
+        // launches, oldest batch first, without the lock
         while (!s.sealed.empty() && (int)s.inflight.size() < s.cfg.n_streams) {
             const int id = s.sealed.front();
             s.sealed.pop_front();
             Slot &sl = s.slots[id];
             sl.state = SlotState::InFlight;
+            ++s.batches;
+            s.batched_events += sl.n_events;
+            lk.unlock();
             const int rc = dispatch(s, sl);
+            lk.lock();
             if (rc != PV_OK && s.worker_error == PV_OK)
                 s.worker_error = rc;
             s.inflight.push_back(id);
-            ++s.batches;
-            s.batched_events += sl.n_events;
         }
         if (s.inflight.empty() && s.sealed.empty() && (s.open < 0 || s.slots[s.open].n_events == 0)) {
             s.cv_work.wait_for(lk, std::chrono::milliseconds(5));
@@ -560,15 +580,19 @@ int pv_server_replay(pv_server *s, const pv_request *reqs, const int64_t *t_offs
     int next = 0, got = 0;
     while (got < n) {
         // submit every request whose arrival time has passed
+        bool busy = false;
         while (next < n && now_ns() >= t0 + t_offset_ns[next]) {
             const int rc = pv_server_submit(s, &reqs[next], (uint64_t)next, t0 + t_offset_ns[next]);
-            if (rc == PV_EBUSY)
-                break;   // retried below; its latency keeps counting from the arrival time
+            if (rc == PV_EBUSY) {
+                busy = true;   // retried after a completion; its latency keeps counting from the arrival
+                break;
+            }
             if (rc != PV_OK)
                 return rc;
             ++next;
         }
-        const int k = pv_server_poll(s, buf.data(), (int32_t)buf.size(), 0);
+        // with every slot taken, wait for a completion rather than spin on the lock
+        const int k = pv_server_poll(s, buf.data(), (int32_t)buf.size(), busy ? 50 : 0);
         if (k < 0)
             return k;
         for (int i = 0; i < k; ++i) {
