@@ -161,7 +161,9 @@ typedef struct {
                                           256, 512 or 1024; larger events go to a
                                           second launch with 4096-track teams         */
     int32_t persistent;                /* 1: persistent grid + device work queue;
-                                          2: one team per event, hardware-scheduled    */
+                                          2: one team per event, hardware-scheduled;
+                                          3: as 1, the queue ordered by decreasing
+                                          track count (a counting-sort launch first)  */
     int32_t teams_per_cu;              /* persistent grid size per compute unit        */
 } pv_schedule;
 

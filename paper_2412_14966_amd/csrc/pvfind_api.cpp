@@ -84,8 +84,8 @@ int validate_schedule(const pv_schedule &s)
         return fail(PV_EINVAL, "schedule: waves_per_team must be 1, 2 or 4 (got %d)", s.waves_per_team);
     if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024)
         return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512 or 1024 (got %d)", s.track_capacity);
-    if (s.persistent != 1 && s.persistent != 2)
-        return fail(PV_EINVAL, "schedule: persistent must be 1 or 2 (got %d)", s.persistent);
+    if (s.persistent < 1 || s.persistent > 3)
+        return fail(PV_EINVAL, "schedule: persistent must be 1, 2 or 3 (got %d)", s.persistent);
     if (s.teams_per_cu < 0 || s.teams_per_cu > 64)
         return fail(PV_EINVAL, "schedule: teams_per_cu out of range (got %d)", s.teams_per_cu);
     return PV_OK;
@@ -176,7 +176,7 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
 }
 
 // Workspace of (current device, stream), grown to hold n_events deferred events.
-int get_workspace(void *stream, int n_events, pvk::WorkQueue **out)
+int get_workspace(void *stream, int n_events, pvk::WorkQueue **out, int32_t **order)
 {
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -195,7 +195,7 @@ int get_workspace(void *stream, int n_events, pvk::WorkQueue **out)
             w.wq = nullptr;
             w.capacity = 0;
         }
-        const size_t bytes = sizeof(pvk::WorkQueue) + sizeof(int) * (size_t)need;
+        const size_t bytes = sizeof(pvk::WorkQueue) + 2 * sizeof(int) * (size_t)need;   // deferred list, order
         void *ptr = nullptr;
         err = hipMalloc(&ptr, bytes);
         if (err != hipSuccess)
@@ -209,6 +209,7 @@ int get_workspace(void *stream, int n_events, pvk::WorkQueue **out)
         w.capacity = need;
     }
     *out = w.wq;
+    *order = pvk::order_list(w.wq, w.capacity);
     return PV_OK;
 }
 
@@ -236,7 +237,9 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         return rc;
     if (n_events == 0)
         return PV_OK;
-    rc = get_workspace(stream, n_events, &A.wq);
+    int32_t *order = nullptr;
+    rc = get_workspace(stream, n_events, &A.wq, &order);
+    A.order = (s.persistent == 3) ? order : nullptr;
     if (rc != PV_OK)
         return rc;
     A.x = tracks->x;
@@ -311,9 +314,9 @@ int schedule_for(const pv_schedule *requested, pv_schedule &out)
     return validate_schedule(out);
 }
 
-int workspace_for(void *stream, int n_events, WorkQueue **out)
+int workspace_for(void *stream, int n_events, WorkQueue **out, int32_t **order)
 {
-    return get_workspace(stream, n_events, out);
+    return get_workspace(stream, n_events, out, order);
 }
 
 }  // namespace pvk
@@ -460,7 +463,7 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
     }
     int rc = PV_OK;
     bool have = false;
-    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[2] = {1, 2};
+    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[3] = {1, 2, 3};
     for (int w : waves)
         for (int c : caps)
             for (int m : modes) {

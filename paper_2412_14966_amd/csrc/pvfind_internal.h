@@ -1,6 +1,7 @@
 // pvfind_internal.h -- definitions shared by the host API and the gfx950 kernels.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "pvfind.h"
@@ -32,9 +33,11 @@ struct KParams {
     float bx, by, btx, bty;
 };
 
-// Device workspace of one stream: work-queue counters and the list of events
-// deferred to the large-team launch.  Counters return to zero at the end of
-// every launch (the last workgroup to finish resets them).
+// Device workspace of one stream: work-queue counters, the list of events
+// deferred to the large-team launch and, behind it, the processing order of
+// the sorted persistent mode (each list holds `capacity` entries).  Counters
+// return to zero at the end of every launch (the last workgroup to finish
+// resets them).
 struct WorkQueue {
     unsigned int next;          // next event index of the main launch
     unsigned int done;          // workgroups of the main launch that finished
@@ -42,7 +45,7 @@ struct WorkQueue {
     unsigned int next_big;      // next deferred event
     unsigned int done_big;      // workgroups of the large-team launch that finished
     unsigned int pad[11];
-    int big[1];                 // n_events entries
+    int big[1];                 // capacity entries, then the order list
 };
 
 struct KArgs {
@@ -62,6 +65,7 @@ struct KArgs {
     int32_t *dbg_bin;
     uint32_t *dbg_cycles;
     WorkQueue *wq;
+    int32_t *order;                 // persistent launches: event order (largest first), or null
     KParams p;
 };
 
@@ -76,7 +80,13 @@ struct LaunchEvents {
 int set_error(int code, const char *fmt, ...);
 int derive_kparams(const pv_params *p, const pv_beamline *bl, KParams &k);
 int schedule_for(const pv_schedule *requested, pv_schedule &out);
-int workspace_for(void *stream, int n_events, WorkQueue **out);
+int workspace_for(void *stream, int n_events, WorkQueue **out, int32_t **order);
+
+// Device address of the order list of a workspace with `capacity` entries per list.
+inline int32_t *order_list(WorkQueue *wq, int capacity)
+{
+    return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(wq) + offsetof(WorkQueue, big)) + capacity;
+}
 
 // Launch one batch on `stream` with schedule `s` (already validated).  With
 // `ev`, events are recorded around the launches.  Returns a hipError_t value.

@@ -758,7 +758,7 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
             } else if (mode == 1) {
                 const unsigned int k = atomicAdd(&A.wq->next, 1u);
                 if (k < (unsigned int)n_events)
-                    e = (int)k;
+                    e = A.order ? A.order[k] : (int)k;
             } else if (first && (int)blockIdx.x < n_events) {
                 e = (int)blockIdx.x;
             }
@@ -788,6 +788,50 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
             __threadfence();
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Processing order for the sorted persistent mode: events by decreasing track
+// count (16-track buckets, the last open-ended), so that the largest events
+// start first and the launch does not end on a long one.  A counting sort by
+// one workgroup; the order within a bucket is unspecified, which the results
+// do not depend on.  Events with invalid offsets go last.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 256;
+
+__global__ __launch_bounds__(1024) void order_events_kernel(const int32_t *offsets, const int32_t *n_events_dev,
+                                                            int32_t n_events_host, int32_t *order)
+{
+    __shared__ int cnt[kOrderBuckets];
+    const int n_events = n_events_dev ? *n_events_dev : n_events_host;
+    const int total = offsets[n_events];
+    auto bucket = [&](int e) -> int {
+        const int a = offsets[e], b = offsets[e + 1];
+        if (a < 0 || b < a || b > total)
+            return 0;
+        return min((b - a) >> 4, kOrderBuckets - 1);
+    };
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x)
+        cnt[k] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_events; e += blockDim.x)
+        atomicAdd(&cnt[bucket(e)], 1);
+    __syncthreads();
+    // exclusive prefix over the buckets, largest first: one wavefront
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int run = 0;
+        for (int k0 = kOrderBuckets - 64; k0 >= 0; k0 -= 64) {
+            const int k = k0 + 63 - lane;   // lane 0 takes the largest bucket of the chunk
+            const int c = cnt[k];
+            const int incl = wave_incl_scan(c, lane);
+            cnt[k] = run + incl - c;
+            run += __shfl(incl, 63);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_events; e += blockDim.x)
+        order[atomicAdd(&cnt[bucket(e)], 1)] = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -850,7 +894,12 @@ template <int W, int CAP, bool DEBUG>
 static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     hipError_t err = record(ev ? ev->main_begin : nullptr, st);
-    const int mode = (s.persistent == 1 || A.n_events_dev) ? 1 : 0;
+    const int mode = (s.persistent != 2 || A.n_events_dev) ? 1 : 0;
+    if (err == hipSuccess && A.order) {
+        hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
+                           A.order);
+        err = hipGetLastError();
+    }
     if (err == hipSuccess)
         err = launch_one<W, CAP, false, DEBUG>(A, mode, s.teams_per_cu, st);
     if (err == hipSuccess)

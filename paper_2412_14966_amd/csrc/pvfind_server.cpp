@@ -119,7 +119,7 @@ size_t slot_device_bytes(const pv_server_config &c, const pv_params &p)
     const size_t T = (size_t)c.max_tracks_per_batch, E = (size_t)c.max_events_per_batch;
     return T * 8 * sizeof(float) + (E + 1) * sizeof(int32_t) + sizeof(int32_t) +
            E * (size_t)p.max_vertices_per_event * sizeof(pv_vertex) + 2 * E * sizeof(int32_t) +
-           T * (sizeof(int32_t) + sizeof(float)) + sizeof(pvk::WorkQueue) + E * sizeof(int32_t);
+           T * (sizeof(int32_t) + sizeof(float)) + sizeof(pvk::WorkQueue) + 2 * E * sizeof(int32_t);
 }
 
 template <typename T>
@@ -156,6 +156,7 @@ pvk::KArgs slot_args(const pv_server &s, const Slot &sl, pvk::WorkQueue *wq, int
     A.trk_vtx = sl.d_tv;
     A.trk_w = sl.d_tw;
     A.wq = wq;
+    A.order = (s.sched.persistent == 3) ? pvk::order_list(wq, s.cfg.max_events_per_batch) : nullptr;
     A.p = s.kp;
     return A;
 }
@@ -197,7 +198,7 @@ int init_slot(pv_server &s, Slot &sl)
     sl.d_tw = reinterpret_cast<float *>(sl.d_tout + T);
     sl.h_tv = sl.h_tout;
     sl.h_tw = reinterpret_cast<float *>(sl.h_tout + T);
-    const size_t wq_bytes = sizeof(pvk::WorkQueue) + sizeof(int32_t) * (size_t)E;
+    const size_t wq_bytes = sizeof(pvk::WorkQueue) + 2 * sizeof(int32_t) * (size_t)E;   // deferred list, order
     hipError_t err = hipMalloc((void **)&sl.wq, wq_bytes);
     if (err != hipSuccess)
         return pvk::set_error(PV_ENOMEM, "hipMalloc: %s", hipGetErrorString(err));

@@ -50,16 +50,17 @@ def check_same_as_batched(batch, host: "pv.HostEvents", ref: "pv.HostResult", co
     assert np.all(comp["t_done_ns"] >= comp["t_arrival_ns"])
 
 
-@pytest.mark.parametrize("graphs", [1, 0])
-def test_served_mix_equals_batched_and_oracle(graphs):
+@pytest.mark.parametrize("graphs,persistent", [(1, 2), (0, 2), (1, 3), (0, 1)])
+def test_served_mix_equals_batched_and_oracle(graphs, persistent):
     batch = synth.generate("served_mulog_200kev", n_events=3000, keep_truth=False)
     params = pv.make_params({"max_vertices_per_event": 96})
-    say(f"served mix graphs={graphs}: {batch.n_events} events, {batch.n_tracks} tracks")
-    ref = pv.run(batch, pv.params_dict(params))
+    sched = dict(waves_per_team=2, track_capacity=512, persistent=persistent, teams_per_cu=0)
+    say(f"served mix graphs={graphs} schedule={sched}: {batch.n_events} events, {batch.n_tracks} tracks")
+    ref = pv.run(batch, pv.params_dict(params), schedule=sched)
     host = pv.HostEvents(batch, params.max_vertices_per_event)
     cfg = pv.pv_server_config_default(max_events_per_batch=512, max_tracks_per_batch=512 * 600, n_slots=4,
                                       n_streams=2, max_wait_us=100, use_graphs=graphs)
-    with pv.Server(params, batch.beamline, cfg) as srv:
+    with pv.Server(params, batch.beamline, cfg, pv.pv_schedule(**sched)) as srv:
         comp = srv.replay(host, poisson_offsets(batch.n_events, 2.0e5, seed=graphs))
         st = srv.stats()
     say(f"served mix graphs={graphs}: stats {st}")
