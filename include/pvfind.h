@@ -163,7 +163,8 @@ typedef struct {
     int32_t persistent;                /* 1: persistent grid + device work queue;
                                           2: one team per event, hardware-scheduled;
                                           3: as 1, the queue ordered by decreasing
-                                          track count (a counting-sort launch first)  */
+                                          track count (a counting-sort launch first);
+                                          4: as 2, teams launched in that order        */
     int32_t teams_per_cu;              /* persistent grid size per compute unit        */
 } pv_schedule;
 

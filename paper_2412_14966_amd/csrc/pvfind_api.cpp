@@ -84,8 +84,8 @@ int validate_schedule(const pv_schedule &s)
         return fail(PV_EINVAL, "schedule: waves_per_team must be 1, 2 or 4 (got %d)", s.waves_per_team);
     if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024)
         return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512 or 1024 (got %d)", s.track_capacity);
-    if (s.persistent < 1 || s.persistent > 3)
-        return fail(PV_EINVAL, "schedule: persistent must be 1, 2 or 3 (got %d)", s.persistent);
+    if (s.persistent < 1 || s.persistent > 4)
+        return fail(PV_EINVAL, "schedule: persistent must be 1, 2, 3 or 4 (got %d)", s.persistent);
     if (s.teams_per_cu < 0 || s.teams_per_cu > 64)
         return fail(PV_EINVAL, "schedule: teams_per_cu out of range (got %d)", s.teams_per_cu);
     return PV_OK;
@@ -239,7 +239,7 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         return PV_OK;
     int32_t *order = nullptr;
     rc = get_workspace(stream, n_events, &A.wq, &order);
-    A.order = (s.persistent == 3) ? order : nullptr;
+    A.order = (s.persistent >= 3) ? order : nullptr;
     if (rc != PV_OK)
         return rc;
     A.x = tracks->x;
@@ -463,7 +463,7 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
     }
     int rc = PV_OK;
     bool have = false;
-    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[3] = {1, 2, 3};
+    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[4] = {1, 2, 3, 4};
     for (int w : waves)
         for (int c : caps)
             for (int m : modes) {

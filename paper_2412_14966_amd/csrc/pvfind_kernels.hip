@@ -760,7 +760,7 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
                 if (k < (unsigned int)n_events)
                     e = A.order ? A.order[k] : (int)k;
             } else if (first && (int)blockIdx.x < n_events) {
-                e = (int)blockIdx.x;
+                e = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
             }
             S.ev = e;
         }
@@ -894,7 +894,7 @@ template <int W, int CAP, bool DEBUG>
 static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     hipError_t err = record(ev ? ev->main_begin : nullptr, st);
-    const int mode = (s.persistent != 2 || A.n_events_dev) ? 1 : 0;
+    const int mode = (s.persistent == 1 || s.persistent == 3 || A.n_events_dev) ? 1 : 0;
     if (err == hipSuccess && A.order) {
         hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
                            A.order);

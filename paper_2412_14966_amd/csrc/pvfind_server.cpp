@@ -156,7 +156,7 @@ pvk::KArgs slot_args(const pv_server &s, const Slot &sl, pvk::WorkQueue *wq, int
     A.trk_vtx = sl.d_tv;
     A.trk_w = sl.d_tw;
     A.wq = wq;
-    A.order = (s.sched.persistent == 3) ? pvk::order_list(wq, s.cfg.max_events_per_batch) : nullptr;
+    A.order = (s.sched.persistent >= 3) ? pvk::order_list(wq, s.cfg.max_events_per_batch) : nullptr;
     A.p = s.kp;
     return A;
 }

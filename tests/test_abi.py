@@ -106,7 +106,7 @@ def test_negative_event_count_and_bad_schedule_rejected():
     assert _call(schedule=pv.pv_schedule(3, 512, 1, 0)) == pv.PV_EINVAL
     assert _call(schedule=pv.pv_schedule(1, 300, 1, 0)) == pv.PV_EINVAL
     assert _call(schedule=pv.pv_schedule(1, 512, 5, 0)) == pv.PV_EINVAL
-    assert _call(schedule=pv.pv_schedule(1, 512, 4, 0)) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(1, 512, 0 - 1, 0)) == pv.PV_EINVAL
 
 
 def test_zero_events_is_a_no_op():
