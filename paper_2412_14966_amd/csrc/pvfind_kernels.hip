@@ -395,6 +395,11 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
 
     Stamps ts;
     stamp<DEBUG>(ts, 0);
+    // the first chunk of tracks is requested before the clear, whose LDS
+    // stores and barrier then overlap the global loads
+    float cur[8];
+    if (tid < n)
+        load_track(A, a + tid, cur);
     // clear
     {
         int4 *h4 = reinterpret_cast<int4 *>(S.u.hist);
@@ -416,10 +421,8 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     // wider ones (about 5 % of tracks at mu = 5) by the whole wavefront, one
     // track at a time, so no lane idles through another lane's long window.
     {
-        float cur[8], nxt[8];
+        float nxt[8];
         unsigned long long words = 0ull;
-        if (tid < n)
-            load_track(A, a + tid, cur);
         for (int i0 = 0; i0 < n; i0 += NT) {
             const int i = i0 + tid;
             const bool valid = i < n;
@@ -485,6 +488,14 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     if (DEBUG && A.dbg_hist)
         for (int j = tid; j < p.nb; j += NT)
             A.dbg_hist[(size_t)e * p.nb + j] = S.u.hist[j];
+    // The gather reads each wavefront's range of tracks again; its first chunk
+    // is requested now, so that the loads complete during the peak search and
+    // the association.
+    const int R = (((n + W - 1) / W) + 63) & ~63;
+    const int r0 = wave * R, r1 = min(n, r0 + R);
+    float gnext[8];
+    if (r0 + lane < r1)
+        load_track(A, a + r0 + lane, gnext);
 
     stamp<DEBUG>(ts, 2);
     // peaks and seeds
@@ -592,8 +603,6 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
         if (lane + 64 < nl)
             S.base[lane + 64] = t0 + i1 - c1;
     }
-    const int R = (((n + W - 1) / W) + 63) & ~63;
-    const int r0 = wave * R, r1 = min(n, r0 + R);
     if (W > 1) {
         for (int k = tid; k < W * kMaxVertices; k += NT)
             (&S.wrun[0][0])[k] = 0;
@@ -619,9 +628,6 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             S.wrun[0][k] = S.base[k];
         __syncthreads();
     }
-    float gnext[8];
-    if (r0 + lane < r1)
-        load_track(A, a + r0 + lane, gnext);
     for (int c0 = r0; c0 < r1; c0 += 64) {
         const int i = c0 + lane;
         const bool valid = i < r1;
