@@ -461,7 +461,7 @@ __device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
 // Each lane keeps up to kRegTracks of its vertex's tracks in registers for
 // all iterations (the rest, if any, is re-read from LDS each iteration).
 // ---------------------------------------------------------------------------
-constexpr int kRegTracks = 8;
+constexpr int kRegTracks = 5;
 
 struct FitSums {
     float s0, sx, sy, szz, gx, gy, gz, sw;

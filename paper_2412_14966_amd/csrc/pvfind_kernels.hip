@@ -39,16 +39,33 @@ namespace pvk {
 // Fit state of the live vertices: position relative to the frame, the last
 // normal matrix (a, b, c, d as in Eq. 14) and n_iter | not_converged << 8 |
 // failed << 9.
+template <int V>
 struct VertexFit {
-    float dx[kMaxVertices], dy[kMaxVertices], dz[kMaxVertices];
-    float a[kMaxVertices], b[kMaxVertices], c[kMaxVertices], d[kMaxVertices];
-    int info[kMaxVertices];
+    float dx[V], dy[V], dz[V];
+    float a[V], b[V], c[V], d[V];
+    int info[V];
 };
 
-template <int W, int CAP>
+constexpr int kPages = 20;          // touched 64-bin histogram words a small team holds
+constexpr int kSmallVertices = 64;  // clusters a small team holds
+
+// LDS of one team.  Large-event teams hold the whole histogram.  Small teams
+// hold only the touched 64-bin words ("pages"): word w lives in page
+// popcount(touched words below w), so touched words that are neighbours in z
+// are neighbours in LDS and every window, run and cluster maps to LDS by one
+// offset.  Events that touch more than kPages words or give more than
+// kSmallVertices clusters go to the large-team launch.
+template <int W, int CAP, bool BIG>
 struct __align__(16) Smem {
+    static constexpr int V = BIG ? kMaxVertices : kSmallVertices;
     union {
-        int hist[kMaxBins];
+        int hist[BIG ? kMaxBins : 1];
+        struct {
+            int pg[kPages * 64];
+            float tz[CAP];   // z_poca of each histogrammed track (small teams, between the passes)
+            float tr[CAP];   // its 1 / (u0 sigma)
+            int tw[CAP];     // its window jl | jh << 16, 0 for none
+        } pp;
         struct {
             float X[CAP];    // track x at the seed z, relative to the seed
             float Y[CAP];
@@ -59,35 +76,68 @@ struct __align__(16) Smem {
         } f;
     } u;
     int tb[CAP];             // (bin + 1) | flags << 13 | (owner + 1) << 16
-    short clo[kMaxVertices], chi[kMaxVertices], cpk[kMaxVertices];
-    float cd0[kMaxVertices]; // seed offset delta * dz from the centre of the peak bin (Eq. 4)
-    short live[kMaxVertices];
-    int pb[kMaxVertices];    // last bin owned by live slot k
-    int cnt[kMaxVertices];   // tracks owned by live slot k
-    int base[kMaxVertices];  // first gathered slot of live slot k
+    short clo[V], chi[V], cpk[V];
+    float cd0[V];            // seed offset delta * dz from the centre of the peak bin (Eq. 4)
+    short live[V];
+    int pb[V];               // last bin owned by live slot k
+    int cnt[V];              // tracks owned by live slot k
+    int base[V];             // first gathered slot of live slot k
     union {
-        int wrun[W][kMaxVertices];   // gather: running slot per wavefront and live slot
-        VertexFit vf;                // fit onwards
+        int wrun[W][V];      // gather: running slot per wavefront and live slot
+        VertexFit<V> vf;     // fit onwards
     };
-    int vout[kMaxVertices];
+    int vout[V];
     short ps[64], pe[64];    // pending proto-clusters
+    int po[64];              // their LDS offsets
     unsigned long long occ;
-    int ev, status, n_cl, n_live, done, n_keep;
+    int ev, status, n_cl, n_live, done, n_keep, defer;
 };
+
+// the histogram as the team holds it: h[j + off] is bin j
+template <int W, int CAP, bool BIG>
+__device__ __forceinline__ int *hist_lds(Smem<W, CAP, BIG> &S)
+{
+    if constexpr (BIG)
+        return S.u.hist;
+    else
+        return S.u.pp.pg;
+}
+
+// page offset of touched word w (small teams): bin j of that word, and of the
+// touched words after it without a gap, is pg[j + page_off(occ, w)]
+__device__ __forceinline__ int page_off(unsigned long long occ, int w)
+{
+    return 64 * (__popcll(occ & ((1ull << w) - 1ull)) - w);
+}
+
+template <int W, int CAP, bool BIG>
+__device__ __forceinline__ int bin_value(Smem<W, CAP, BIG> &S, unsigned long long occ, int j)
+{
+    if constexpr (BIG) {
+        return S.u.hist[j];
+    } else {
+        const int w = j >> 6;
+        return ((occ >> w) & 1ull) ? S.u.pp.pg[j + page_off(occ, w)] : 0;
+    }
+}
 
 // Whole peak search, run by wavefront 0.  Proto-cluster runs come from
 // ballots of (bin > proto_thr) over the touched 64-bin words; they are queued
 // and walked 32-64 at a time, one lane per proto-cluster.
-template <int W, int CAP>
-__device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
+template <int W, int CAP, bool BIG>
+__device__ __forceinline__ void peak_search(Smem<W, CAP, BIG> &S, const KParams &p)
 {
     const int lane = threadIdx.x & 63;
-    int n_found = 0, npend = 0, open_s = -1, prev_w = -2;
-    unsigned long long occ = S.occ;
-    auto push = [&](int s, int e) __attribute__((always_inline)) {
+    int *h = hist_lds(S);
+    const int cap = BIG ? p.max_vertices : min(p.max_vertices, Smem<W, CAP, BIG>::V);
+    int n_found = 0, npend = 0, open_s = -1, open_off = 0, prev_w = -2, pgi = 0;
+    const unsigned long long occ0 = S.occ;
+    unsigned long long occ = occ0;
+    auto push = [&](int s, int e, int off) __attribute__((always_inline)) {
         if (lane == 0) {
             S.ps[npend] = (short)s;
             S.pe[npend] = (short)e;
+            S.po[npend] = off;
         }
         ++npend;
     };
@@ -97,22 +147,24 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
             // one word adds at most 32 runs plus the close of an open one
             const int w = __ffsll((long long)occ) - 1;
             occ &= occ - 1ull;
+            const int off = BIG ? 0 : 64 * (pgi - w);
             if (open_s >= 0 && prev_w != w - 1) {
-                push(open_s, 64 * prev_w + 63);
+                push(open_s, 64 * prev_w + 63, open_off);
                 open_s = -1;
             }
             const int j = 64 * w + lane;
-            const int hv = (j < p.nb) ? S.u.hist[j] : 0;
+            const int hv = (j < p.nb) ? h[j + off] : 0;
             const unsigned long long m = __ballot(hv > p.proto_thr);
             unsigned long long st = m & ~(m << 1);
             unsigned long long en = m & ~(m >> 1);
-            int cur = -1;
+            int cur = -1, cur_off = off;
             if (open_s >= 0) {
                 if (m & 1ull) {
                     cur = open_s;
+                    cur_off = open_off;
                     st &= ~1ull;
                 } else {
-                    push(open_s, 64 * w - 1);
+                    push(open_s, 64 * w - 1, open_off);
                 }
                 open_s = -1;
             }
@@ -123,35 +175,40 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
                     const int sb = __ffsll((long long)st) - 1;
                     st &= st - 1ull;
                     cur = 64 * w + sb;
+                    cur_off = off;
                 }
-                if (eb == 63)
+                if (eb == 63) {
                     open_s = cur;
-                else
-                    push(cur, 64 * w + eb);
+                    open_off = cur_off;
+                } else {
+                    push(cur, 64 * w + eb, cur_off);
+                }
                 cur = -1;
             }
             prev_w = w;
+            ++pgi;
         } else if (open_s >= 0) {
-            push(open_s, 64 * prev_w + 63);
+            push(open_s, 64 * prev_w + 63, open_off);
             open_s = -1;
         }
         __builtin_amdgcn_wave_barrier();
         if (npend >= 32 || (last && npend > 0)) {
             const bool has = lane < npend;
-            int s = 0, e = 0;
+            int s = 0, e = 0, off = 0;
             if (has) {
                 s = S.ps[lane];
                 e = S.pe[lane];
+                off = S.po[lane];
             }
-            const int tot = has ? sum_bins(S.u.hist, 0, s, e) : 0;
+            const int tot = has ? sum_bins(h, off, s, e) : 0;
             WalkOut wo{{0u, 0u, 0u, 0u}, 0, -1};
-            const int c = has ? walk_proto<false>(S.u.hist, 0, p, s, e, tot, wo, nullptr, nullptr, nullptr, 0, 0) : 0;
+            const int c = has ? walk_proto<false>(h, off, p, s, e, tot, wo, nullptr, nullptr, nullptr, 0, 0) : 0;
             const int incl = wave_incl_scan(c, lane);
             const int first = n_found + incl - c;
             if (has && wo.nsplit > 4)   // rare: more splits than recorded
-                walk_proto<true>(S.u.hist, 0, p, s, e, tot, wo, S.clo, S.chi, S.cpk, p.max_vertices, first);
+                walk_proto<true>(h, off, p, s, e, tot, wo, S.clo, S.chi, S.cpk, cap, first);
             else if (has)
-                write_walk(wo, s, e, S.clo, S.chi, S.cpk, p.max_vertices, first);
+                write_walk(wo, s, e, S.clo, S.chi, S.cpk, cap, first);
             n_found += __shfl(incl, 63);
             npend = 0;
             __builtin_amdgcn_wave_barrier();
@@ -160,14 +217,14 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
             break;
     }
 
-    const int ncl = min(n_found, p.max_vertices);
+    __builtin_amdgcn_wave_barrier();
+    const int ncl = min(n_found, cap);
     // seeds (Eq. 4-5): first highest bin (found by the walk), correction from the neighbours
     for (int q = lane; q < ncl; q += 64) {
-        const int *h = S.u.hist;
         const int im = S.cpk[q];
-        const int Ni = h[im];
-        const int Nm = (im > 0) ? h[im - 1] : 0;
-        const int Np = (im + 1 < p.nb) ? h[im + 1] : 0;
+        const int Ni = bin_value(S, occ0, im);
+        const int Nm = (im > 0) ? bin_value(S, occ0, im - 1) : 0;
+        const int Np = (im + 1 < p.nb) ? bin_value(S, occ0, im + 1) : 0;
         const int den = 2 * Ni - Np - Nm;
         float delta = (den > 0) ? 0.5f * (float)(Np - Nm) / (float)den : 0.0f;
         delta = fminf(fmaxf(delta, -0.5f), 0.5f);
@@ -177,13 +234,15 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP> &S, const KParams &p)
         S.n_cl = ncl;
         if (n_found > p.max_vertices)
             S.status |= PV_EV_VERTEX_OVERFLOW;
+        // more clusters than a small team holds, where the caller allows more
+        S.defer = (!BIG && n_found > cap && p.max_vertices > cap) ? 1 : 0;
     }
 }
 
 // L = 1 << lg lanes per vertex, wavefront-uniform (scalar): one copy of the
 // code serves every group size.
-template <int W, int CAP>
-__device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, int nl, int L, int lg)
+template <int W, int CAP, bool BIG>
+__device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams &p, int nl, int L, int lg)
 {
     constexpr int NT = 64 * W;
     const int G = NT >> lg;
@@ -276,8 +335,8 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP> &S, const KParams &p, 
 
 // Final Tukey weights at the fitted position, per-track outputs, chi2 and
 // ndof (2 sum w - 3), covariance (Eq. 14) and the vertex record.
-template <int W, int CAP>
-__device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int e, int a, int nl, int L, int lg)
+template <int W, int CAP, bool BIG>
+__device__ __forceinline__ void final_pass(Smem<W, CAP, BIG> &S, const KArgs &A, int e, int a, int nl, int L, int lg)
 {
     constexpr int NT = 64 * W;
     const int G = NT >> lg;
@@ -356,7 +415,7 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP> &S, const KArgs &A, int 
 // one event
 // ---------------------------------------------------------------------------
 template <int W, int CAP, bool BIG, bool DEBUG>
-__device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, int e, int n_events)
+__device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs &A, int e, int n_events)
 {
     constexpr int NT = 64 * W;
     const KParams &p = A.p;
@@ -395,31 +454,63 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
 
     Stamps ts;
     stamp<DEBUG>(ts, 0);
+    auto defer = [&]() __attribute__((always_inline)) {
+        if (tid == 0) {
+            const unsigned int k = atomicAdd(&A.wq->n_big, 1u);
+            A.wq->big[k] = e;
+        }
+    };
+    int *h = hist_lds(S);
     // the first chunk of tracks is requested before the clear, whose LDS
     // stores and barrier then overlap the global loads
     float cur[8];
     if (tid < n)
         load_track(A, a + tid, cur);
-    // clear
-    {
+    // clear (large teams: the whole histogram; small teams clear their pages
+    // once the touched words are known)
+    if constexpr (BIG) {
         int4 *h4 = reinterpret_cast<int4 *>(S.u.hist);
         const int n4 = (p.nb + 3) >> 2;
         for (int i = tid; i < n4; i += NT)
             h4[i] = make_int4(0, 0, 0, 0);
-        if (tid == 0) {
-            S.occ = 0ull;
-            S.status = 0;
-            S.done = 0;
-        }
+    }
+    if (tid == 0) {
+        S.occ = 0ull;
+        S.status = 0;
+        S.done = 0;
     }
     __syncthreads();
     stamp<DEBUG>(ts, 1);
 
-    // project + fill.  All lanes run every chunk (wavefront-wide steps below);
-    // the loads of the next chunk are issued before this chunk is filled.
     // Kernel windows of up to kShortWindow bins are filled by their own lane;
     // wider ones (about 5 % of tracks at mu = 5) by the whole wavefront, one
     // track at a time, so no lane idles through another lane's long window.
+    // `off` maps a window's bins to LDS (0 for the whole histogram).
+    auto fill_chunk = [&](bool has, float zp, float rinv, Window w, int off) __attribute__((always_inline)) {
+        const bool wide = has && (w.jh - w.jl) > kShortWindow;
+        if (has && !wide)
+            fill_short(h, off, w, zp, rinv, p);
+        unsigned long long wm = __ballot(wide);
+        while (wm) {
+            const int src = __ffsll((long long)wm) - 1;
+            wm &= wm - 1ull;
+            const float zs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zp), src));
+            const float rs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rinv), src));
+            const int jl = __builtin_amdgcn_readlane(w.jl, src);
+            const int jh = __builtin_amdgcn_readlane(w.jh, src);
+            const int os = __builtin_amdgcn_readlane(off, src);
+            for (int j = jl + lane; j < jh; j += 64) {
+                const int d = code_at(j + 1, zs, rs, p) - code_at(j, zs, rs, p);
+                if (d != 0)
+                    atomicAdd(&h[j + os], d);
+            }
+        }
+    };
+
+    // project (+ fill for large teams).  All lanes run every chunk
+    // (wavefront-wide steps above); the loads of the next chunk are issued
+    // before this chunk is processed.  Small teams record each histogrammed
+    // track's z_poca, 1 / (u0 sigma) and window for the fill pass.
     {
         float nxt[8];
         unsigned long long words = 0ull;
@@ -431,7 +522,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             Proj r{0.0f, 0.0f, -1, 0};
             if (valid)
                 r = project(cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], cur[6], cur[7], p);
-            bool wide = false;
+            bool has = false;
             float rinv = 0.0f;
             Window w{0, 0};
             if (r.fl & kTrHist) {
@@ -440,29 +531,20 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
                 w = track_window(r.zp, sw, p);
                 if (w.jh > w.jl) {
                     words |= window_words(w);
-                    wide = (w.jh - w.jl) > kShortWindow;
-                    if (!wide)
-                        fill_short(S.u.hist, 0, w, r.zp, rinv, p);
+                    has = true;
                 }
             }
-            unsigned long long wm = __ballot(wide);
-            while (wm) {
-                const int src = __ffsll((long long)wm) - 1;
-                wm &= wm - 1ull;
-                const float zs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.zp), src));
-                const float rs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rinv), src));
-                const int jl = __builtin_amdgcn_readlane(w.jl, src);
-                const int jh = __builtin_amdgcn_readlane(w.jh, src);
-                for (int j = jl + lane; j < jh; j += 64) {
-                    const int d = code_at(j + 1, zs, rs, p) - code_at(j, zs, rs, p);
-                    if (d != 0)
-                        atomicAdd(&S.u.hist[j], d);
-                }
-            }
+            if constexpr (BIG)
+                fill_chunk(has, r.zp, rinv, w, 0);
             if (valid) {
                 if (r.fl & kTrNonfinite)
                     atomicOr(&S.status, PV_EV_NONFINITE_INPUT);
                 S.tb[i] = (r.bin + 1) | (r.fl << 13);
+                if constexpr (!BIG) {
+                    S.u.pp.tz[i] = r.zp;
+                    S.u.pp.tr[i] = rinv;
+                    S.u.pp.tw[i] = has ? (w.jl | (w.jh << 16)) : 0;
+                }
                 if (DEBUG) {
                     const int g = a + i;
                     if (A.dbg_zp)
@@ -485,9 +567,43 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             atomicOr(&S.occ, words);
     }
     __syncthreads();
-    if (DEBUG && A.dbg_hist)
+    if constexpr (!BIG) {
+        const unsigned long long occ = S.occ;
+        const int npg = __popcll(occ);
+        if (npg > kPages) {
+            defer();
+            return;
+        }
+        int4 *h4 = reinterpret_cast<int4 *>(S.u.pp.pg);
+        for (int k = tid; k < npg * 16; k += NT)
+            h4[k] = make_int4(0, 0, 0, 0);
+        __syncthreads();
+        // fill: each touched word's bins sit at one offset
+        for (int i0 = 0; i0 < n; i0 += NT) {
+            const int i = i0 + tid;
+            float zp = 0.0f, rinv = 0.0f;
+            Window w{0, 0};
+            int off = 0;
+            bool has = false;
+            if (i < n) {
+                const int tw = S.u.pp.tw[i];
+                if (tw != 0) {
+                    w = Window{tw & 0xFFFF, tw >> 16};
+                    zp = S.u.pp.tz[i];
+                    rinv = S.u.pp.tr[i];
+                    off = page_off(occ, w.jl >> 6);
+                    has = true;
+                }
+            }
+            fill_chunk(has, zp, rinv, w, off);
+        }
+        __syncthreads();
+    }
+    if (DEBUG && A.dbg_hist) {
+        const unsigned long long occ = S.occ;
         for (int j = tid; j < p.nb; j += NT)
-            A.dbg_hist[(size_t)e * p.nb + j] = S.u.hist[j];
+            A.dbg_hist[(size_t)e * p.nb + j] = bin_value(S, occ, j);
+    }
     // The gather reads each wavefront's range of tracks again; its first chunk
     // is requested now, so that the loads complete during the peak search and
     // the association.
@@ -502,6 +618,10 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     if (wave == 0)
         peak_search(S, p);
     __syncthreads();
+    if (!BIG && S.defer) {
+        defer();
+        return;
+    }
     stamp<DEBUG>(ts, 3);
 
     // association with iterative removal (Sec. 3.4)
@@ -604,7 +724,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
             S.base[lane + 64] = t0 + i1 - c1;
     }
     if (W > 1) {
-        for (int k = tid; k < W * kMaxVertices; k += NT)
+        for (int k = tid; k < W * Smem<W, CAP, BIG>::V; k += NT)
             (&S.wrun[0][0])[k] = 0;
         __syncthreads();
         for (int i = r0 + lane; i < r1; i += 64) {
@@ -689,7 +809,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     }
     lg = __builtin_amdgcn_readfirstlane(lg);   // the same on every lane: keep it scalar
     const int L = 1 << lg;
-    fit_vertices<W, CAP>(S, p, nl, L, lg);
+    fit_vertices<W, CAP, BIG>(S, p, nl, L, lg);
     __syncthreads();
     stamp<DEBUG>(ts, 6);
 
@@ -725,7 +845,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
     stamp<DEBUG>(ts, 7);
 
     // final weights, vertex records
-    final_pass<W, CAP>(S, A, e, a, nl, L, lg);
+    final_pass<W, CAP, BIG>(S, A, e, a, nl, L, lg);
     if (tid == 0) {
         A.nv_out[e] = S.n_keep;
         A.status_out[e] = S.status;
@@ -744,7 +864,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP> &S, const KArgs &A, i
 template <int W, int CAP, bool BIG, bool DEBUG>
 __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
 {
-    __shared__ Smem<W, CAP> S;
+    __shared__ Smem<W, CAP, BIG> S;
     const int tid = threadIdx.x;
     const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
     // Nothing deferred: the large-team counters are all zero and stay so; leave
