@@ -87,31 +87,26 @@ __device__ __forceinline__ float group_sum_rt(float v, int L)
     return v;
 }
 
-// The eight sums of one Newton step at once, for a wavefront-uniform L: the
-// in-row levels are branch-free; the two cross-row levels, which go through
-// the LDS crossbar, run only for groups of 32 and 64 lanes.
-__device__ __forceinline__ void group_sum8_rt(float v[8], int L)
+// The eight sums of one Newton step at once, for a wavefront-uniform group of
+// L = 1 << lg lanes: one scalar branch picks the butterfly for that L.
+template <int L>
+__device__ __forceinline__ void group_sum8(float v[8])
 {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        float t = dpp_f<0xB1>(v[k]);
-        v[k] = (L >= 2) ? v[k] + t : v[k];
-        t = dpp_f<0x4E>(v[k]);
-        v[k] = (L >= 4) ? v[k] + t : v[k];
-        t = dpp_f<0x141>(v[k]);
-        v[k] = (L >= 8) ? v[k] + t : v[k];
-        t = dpp_f<0x140>(v[k]);
-        v[k] = (L >= 16) ? v[k] + t : v[k];
-    }
-    if (L >= 32) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            v[k] += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v[k]), 0x401F));
-    }
-    if (L >= 64) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            v[k] += __shfl_xor(v[k], 32);
+    for (int k = 0; k < 8; ++k)
+        v[k] = group_sum<L>(v[k]);
+}
+
+__device__ __forceinline__ void group_sum8_rt(float v[8], int lg)
+{
+    switch (lg) {
+    case 0: break;
+    case 1: group_sum8<2>(v); break;
+    case 2: group_sum8<4>(v); break;
+    case 3: group_sum8<8>(v); break;
+    case 4: group_sum8<16>(v); break;
+    case 5: group_sum8<32>(v); break;
+    default: group_sum8<64>(v); break;
     }
 }
 
@@ -470,24 +465,23 @@ struct FitSums {
 __device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float tx, float ty, float wt, float dx,
                                            float dy, float dz, const KParams &p)
 {
-    // residual (Eq. 9) relative to the frame origin, chi2 (Eq. 7), Tukey weight (Eq. 17)
+    // residual (Eq. 9) relative to the frame origin, chi2 (Eq. 7), Tukey weight
+    // (Eq. 17; zero beyond chi2_max, where the terms below add exact zeros)
     const float rx = fmaf(dz, tx, X) - dx;
     const float ry = fmaf(dz, ty, Y) - dy;
     const float chi2 = wt * fmaf(rx, rx, ry * ry);
-    if (chi2 < p.chi2_max) {
-        const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
-        const float w = u * u;
-        const float ww = w * wt;
-        a.sw += w;
-        a.s0 += ww;
-        a.sx = fmaf(ww, tx, a.sx);
-        a.sy = fmaf(ww, ty, a.sy);
-        a.szz = fmaf(ww, fmaf(tx, tx, ty * ty), a.szz);
-        const float px = ww * rx, py = ww * ry;
-        a.gx += px;
-        a.gy += py;
-        a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
-    }
+    const float u = (chi2 < p.chi2_max) ? fmaf(-chi2, p.inv_chi2_max, 1.0f) : 0.0f;
+    const float w = u * u;
+    const float ww = w * wt;
+    a.sw += w;
+    a.s0 += ww;
+    a.sx = fmaf(ww, tx, a.sx);
+    a.sy = fmaf(ww, ty, a.sy);
+    a.szz = fmaf(ww, fmaf(tx, tx, ty * ty), a.szz);
+    const float px = ww * rx, py = ww * ry;
+    a.gx += px;
+    a.gy += py;
+    a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
 }
 
 // Stage boundaries for the per-stage cycle counters of the debug variant.

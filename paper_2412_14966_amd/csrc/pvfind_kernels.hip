@@ -289,7 +289,7 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
                 }
             }
             float r[8] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz, a.sw};
-            group_sum8_rt(r, L);
+            group_sum8_rt(r, lg);
             const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6], sw = r[7];
             if (active) {
                 // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
