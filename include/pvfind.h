@@ -160,11 +160,16 @@ typedef struct {
     int32_t track_capacity;            /* tracks per event held in LDS by small teams:
                                           256, 512 or 1024; larger events go to a
                                           second launch with 4096-track teams         */
-    int32_t persistent;                /* 1: persistent grid + device work queue;
-                                          2: one team per event, hardware-scheduled;
-                                          3: as 1, the queue ordered by decreasing
-                                          track count (a counting-sort launch first);
-                                          4: as 2, teams launched in that order        */
+    int32_t persistent;                /* 2: one team per event, hardware-scheduled;
+                                          4: as 2, teams launched in the order of a
+                                          counting sort by decreasing track count
+                                          (one small launch first).  1 and 3 (a
+                                          persistent grid popping a device work queue,
+                                          unsorted / sorted) are rejected: with events
+                                          handed to the large-team launch part-way
+                                          they did not finish on the GPU, for a reason
+                                          not found.  Large-event teams always run
+                                          persistent.                                 */
     int32_t teams_per_cu;              /* persistent grid size per compute unit        */
 } pv_schedule;
 

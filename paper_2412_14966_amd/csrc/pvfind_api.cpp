@@ -30,7 +30,7 @@ int fail(int code, const char *fmt, ...)
 }
 
 std::mutex g_mu;
-pv_schedule g_sched = {2, 512, 2, 0};   // fastest measured at mu = 5 before pv_autotune runs
+pv_schedule g_sched = {2, 512, 4, 0};   // fastest measured at mu = 5 before pv_autotune runs
 
 // benchmark timing records
 std::mutex g_tmu;
@@ -86,6 +86,9 @@ int validate_schedule(const pv_schedule &s)
         return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512 or 1024 (got %d)", s.track_capacity);
     if (s.persistent < 1 || s.persistent > 4)
         return fail(PV_EINVAL, "schedule: persistent must be 1, 2, 3 or 4 (got %d)", s.persistent);
+    if (s.persistent == 1 || s.persistent == 3)
+        return fail(PV_EINVAL, "schedule: persistent small-team launches (modes 1 and 3) are disabled; "
+                               "use 2 or 4");
     if (s.teams_per_cu < 0 || s.teams_per_cu > 64)
         return fail(PV_EINVAL, "schedule: teams_per_cu out of range (got %d)", s.teams_per_cu);
     return PV_OK;
@@ -463,7 +466,7 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
     }
     int rc = PV_OK;
     bool have = false;
-    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[4] = {1, 2, 3, 4};
+    const int waves[3] = {1, 2, 4}, caps[3] = {256, 512, 1024}, modes[2] = {2, 4};
     for (int w : waves)
         for (int c : caps)
             for (int m : modes) {

@@ -916,6 +916,21 @@ __global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
     }
 }
 
+// One small team per event, hardware-scheduled (grid = events, or the batch
+// capacity when the count is read from device memory).  Without the
+// persistent loop no value has to live from one event to the next, which
+// keeps the register footprint far below the persistent kernel's.
+template <int W, int CAP, bool DEBUG>
+__global__ __launch_bounds__(64 * W) void pv_find_single(KArgs A)
+{
+    __shared__ Smem<W, CAP, false> S;
+    const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
+    if ((int)blockIdx.x >= n_events)
+        return;
+    const int e = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
+    process_event<W, CAP, false, DEBUG>(S, A, e, n_events);
+}
+
 // ---------------------------------------------------------------------------
 // Processing order for the sorted persistent mode: events by decreasing track
 // count (16-track buckets, the last open-ended), so that the largest events
@@ -987,6 +1002,12 @@ static int device_cus()
 template <int W, int CAP, bool BIG, bool DEBUG>
 static hipError_t launch_one(const KArgs &A, int mode, int teams_per_cu, hipStream_t st)
 {
+    if (!BIG && mode == 0) {
+        if (A.n_events < 1)
+            return hipSuccess;
+        hipLaunchKernelGGL((pv_find_single<W, CAP, DEBUG>), dim3(A.n_events), dim3(64 * W), 0, st, A);
+        return hipGetLastError();
+    }
     auto *fn = pv_find_kernel<W, CAP, BIG, DEBUG>;
     int grid;
     if (mode == 1 || BIG) {
@@ -1020,7 +1041,7 @@ template <int W, int CAP, bool DEBUG>
 static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     hipError_t err = record(ev ? ev->main_begin : nullptr, st);
-    const int mode = (s.persistent == 1 || s.persistent == 3 || A.n_events_dev) ? 1 : 0;
+    const int mode = (s.persistent == 1 || s.persistent == 3) ? 1 : 0;
     if (err == hipSuccess && A.order) {
         hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
                            A.order);
@@ -1032,8 +1053,10 @@ static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t 
         err = record(ev ? ev->main_end : nullptr, st);
     if (err != hipSuccess)
         return err;
-    // events with more tracks than CAP were deferred to the large-team launch
-    if (A.p.max_tracks > CAP) {
+    // events with more tracks than CAP, more touched histogram words than the
+    // pages or more clusters than the vertex slots of a small team were
+    // deferred to the large-team launch (which returns at once if none was)
+    {
         if (ev)
             ev->large = true;
         err = record(ev ? ev->large_begin : nullptr, st);

@@ -151,7 +151,7 @@ def pv_nbins(params: Optional[pv_params] = None) -> int:
     return lib().pv_nbins(ctypes.byref(params or pv_params_default()))
 
 
-def pv_set_schedule(waves_per_team=1, track_capacity=512, persistent=1, teams_per_cu=0):
+def pv_set_schedule(waves_per_team=2, track_capacity=512, persistent=2, teams_per_cu=0):
     _check(lib().pv_set_schedule(ctypes.byref(pv_schedule(waves_per_team, track_capacity, persistent,
                                                           teams_per_cu))))
 

@@ -103,10 +103,12 @@ def test_bad_params_rejected(field, value):
 
 def test_negative_event_count_and_bad_schedule_rejected():
     assert _call(n_events=-1) == pv.PV_EINVAL
-    assert _call(schedule=pv.pv_schedule(3, 512, 1, 0)) == pv.PV_EINVAL
-    assert _call(schedule=pv.pv_schedule(1, 300, 1, 0)) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(3, 512, 2, 0)) == pv.PV_EINVAL
+    assert _call(schedule=pv.pv_schedule(1, 300, 2, 0)) == pv.PV_EINVAL
     assert _call(schedule=pv.pv_schedule(1, 512, 5, 0)) == pv.PV_EINVAL
     assert _call(schedule=pv.pv_schedule(1, 512, 0 - 1, 0)) == pv.PV_EINVAL
+    for disabled in (1, 3):   # persistent small-team launches
+        assert _call(schedule=pv.pv_schedule(2, 512, disabled, 0)) == pv.PV_EINVAL
 
 
 def test_zero_events_is_a_no_op():

@@ -50,7 +50,7 @@ def check_same_as_batched(batch, host: "pv.HostEvents", ref: "pv.HostResult", co
     assert np.all(comp["t_done_ns"] >= comp["t_arrival_ns"])
 
 
-@pytest.mark.parametrize("graphs,persistent", [(1, 2), (0, 2), (1, 3), (0, 1), (0, 4)])
+@pytest.mark.parametrize("graphs,persistent", [(1, 2), (0, 2), (1, 4), (0, 4)])
 def test_served_mix_equals_batched_and_oracle(graphs, persistent):
     batch = synth.generate("served_mulog_200kev", n_events=3000, keep_truth=False)
     params = pv.make_params({"max_vertices_per_event": 96})
