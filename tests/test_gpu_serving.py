@@ -50,7 +50,14 @@ def check_same_as_batched(batch, host: "pv.HostEvents", ref: "pv.HostResult", co
     assert np.all(comp["t_done_ns"] >= comp["t_arrival_ns"])
 
 
-@pytest.mark.parametrize("graphs,persistent", [(1, 2), (0, 2), (1, 4), (0, 4)])
+_PERSISTENT_OFF = pytest.mark.skip(reason="persistent small-team schedules are rejected by the library: a persistent "
+                                          "launch handing events to the large-team launch part-way did not finish "
+                                          "on the GPU, cause not found")
+
+
+@pytest.mark.parametrize("graphs,persistent", [(1, 2), (0, 2), (1, 4), (0, 4),
+                                               pytest.param(1, 3, marks=_PERSISTENT_OFF),
+                                               pytest.param(0, 1, marks=_PERSISTENT_OFF)])
 def test_served_mix_equals_batched_and_oracle(graphs, persistent):
     batch = synth.generate("served_mulog_200kev", n_events=3000, keep_truth=False)
     params = pv.make_params({"max_vertices_per_event": 96})
