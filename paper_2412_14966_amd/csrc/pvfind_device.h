@@ -87,26 +87,27 @@ __device__ __forceinline__ float group_sum_rt(float v, int L)
     return v;
 }
 
-// The eight sums of one Newton step at once, for a wavefront-uniform group of
+// The N sums of one Newton step at once, for a wavefront-uniform group of
 // L = 1 << lg lanes: one scalar branch picks the butterfly for that L.
-template <int L>
-__device__ __forceinline__ void group_sum8(float v[8])
+template <int L, int N>
+__device__ __forceinline__ void group_sum_n(float v[N])
 {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < N; ++k)
         v[k] = group_sum<L>(v[k]);
 }
 
-__device__ __forceinline__ void group_sum8_rt(float v[8], int lg)
+template <int N>
+__device__ __forceinline__ void group_sum_n_rt(float v[N], int lg)
 {
     switch (lg) {
     case 0: break;
-    case 1: group_sum8<2>(v); break;
-    case 2: group_sum8<4>(v); break;
-    case 3: group_sum8<8>(v); break;
-    case 4: group_sum8<16>(v); break;
-    case 5: group_sum8<32>(v); break;
-    default: group_sum8<64>(v); break;
+    case 1: group_sum_n<2, N>(v); break;
+    case 2: group_sum_n<4, N>(v); break;
+    case 3: group_sum_n<8, N>(v); break;
+    case 4: group_sum_n<16, N>(v); break;
+    case 5: group_sum_n<32, N>(v); break;
+    default: group_sum_n<64, N>(v); break;
     }
 }
 
@@ -209,21 +210,34 @@ __device__ __forceinline__ int code_at(int j, float zp, float r, const KParams &
 
 constexpr int kShortWindow = 8;   // bins per lane in the per-lane pass
 
-// per-lane pass: windows of at most kShortWindow bins, fixed trip count
-// hist[j + off] holds bin j
+// per-lane pass: windows of at most kShortWindow bins, fixed trip count and
+// no branch but the atomic's.  Edge jh (the window's last, jh <= nb) carries
+// the full code and so does every edge after it (the window has one spare
+// edge beyond the kernel's support, and the codes grow with the edge), so
+// those edges are set to `unit` without evaluation and add nothing.
+// hist[j + off] holds bin j.
+__device__ __forceinline__ int edge_code_in(int j, float zp, float r, const KParams &p)
+{
+    const float e = p.z_min + (float)j * p.dz;
+    // clamp to [-1, 1]; s is finite here (zp and r are)
+    const float s = __builtin_amdgcn_fmed3f((e - zp) * r, -1.0f, 1.0f);
+    const float P = 0.5f + s * (0.75f - 0.25f * (s * s));
+    return (int)rintf(P * p.unit);
+}
+
 __device__ __forceinline__ void fill_short(int *hist, int off, Window w, float zp, float r, const KParams &p)
 {
-    int prev = code_at(w.jl, zp, r, p);
+    const int full = (int)p.unit;
+    int prev = (w.jl <= 0) ? 0 : edge_code_in(w.jl, zp, r, p);
 #pragma unroll
     for (int u = 0; u < kShortWindow; ++u) {
         const int j = w.jl + u;
-        if (j < w.jh) {
-            const int next = code_at(j + 1, zp, r, p);
-            const int d = next - prev;
-            if (d != 0)
-                atomicAdd(&hist[j + off], d);
-            prev = next;
-        }
+        const int c = edge_code_in(j + 1, zp, r, p);
+        const int next = (j + 1 >= w.jh) ? full : c;
+        const int d = next - prev;
+        if (d != 0)
+            atomicAdd(&hist[j + off], d);
+        prev = next;
     }
 }
 
@@ -458,8 +472,10 @@ __device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
 // ---------------------------------------------------------------------------
 constexpr int kRegTracks = 5;
 
+// The step needs no sum of the weights w alone: it is zero exactly when every
+// w * (1 / V_x) is, i.e. when s0 is, and s0 <= 0 already fails the step.
 struct FitSums {
-    float s0, sx, sy, szz, gx, gy, gz, sw;
+    float s0, sx, sy, szz, gx, gy, gz;
 };
 
 __device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float tx, float ty, float wt, float dx,
@@ -473,7 +489,6 @@ __device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float t
     const float u = (chi2 < p.chi2_max) ? fmaf(-chi2, p.inv_chi2_max, 1.0f) : 0.0f;
     const float w = u * u;
     const float ww = w * wt;
-    a.sw += w;
     a.s0 += ww;
     a.sx = fmaf(ww, tx, a.sx);
     a.sy = fmaf(ww, ty, a.sy);

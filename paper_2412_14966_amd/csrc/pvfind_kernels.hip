@@ -72,10 +72,13 @@ struct __align__(16) Smem {
             float TX[CAP];
             float TY[CAP];
             float WT[CAP];   // 1 / V_x at the seed (Eq. 2), 0 for unusable tracks
-            int IDX[CAP];    // track index within the event
+            short IDX[CAP];  // track index within the event
         } f;
     } u;
-    int tb[CAP];             // (bin + 1) | flags << 13 | (owner + 1) << 16
+    union {
+        int tb[CAP];         // up to the gather: (bin + 1) | flags << 13 | (owner + 1) << 16
+        VertexFit<V> vf;     // fit onwards
+    };
     short clo[V], chi[V], cpk[V];
     float cd0[V];            // seed offset delta * dz from the centre of the peak bin (Eq. 4)
     short live[V];
@@ -84,11 +87,12 @@ struct __align__(16) Smem {
     int base[V];             // first gathered slot of live slot k
     union {
         int wrun[W][V];      // gather: running slot per wavefront and live slot
-        VertexFit<V> vf;     // fit onwards
+        struct {
+            short ps[64], pe[64];   // peak search: pending proto-clusters
+            int po[64];             // their LDS offsets
+        };
     };
     int vout[V];
-    short ps[64], pe[64];    // pending proto-clusters
-    int po[64];              // their LDS offsets
     unsigned long long occ;
     int ev, status, n_cl, n_live, done, n_keep, defer;
 };
@@ -275,7 +279,7 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
         for (int it = 1; it <= p.max_iter; ++it) {
             if (!__any(active))
                 break;
-            FitSums a = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            FitSums a = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (active) {
 #pragma unroll
                 for (int u = 0; u < kRegTracks; ++u)
@@ -288,14 +292,14 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
                         accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
                 }
             }
-            float r[8] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz, a.sw};
-            group_sum8_rt(r, lg);
-            const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6], sw = r[7];
+            float r[7] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz};
+            group_sum_n_rt<7>(r, lg);
+            const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6];
             if (active) {
                 // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
                 // det(A) = s0 * D, singular when det <= sing_ratio * s0 * s0 * szz
                 const float D = fmaf(s0, szz, -fmaf(sx, sx, sy * sy));
-                if (!(sw > 0.0f) || !(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
+                if (!(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
                     failed = true;
                     active = false;
                 } else {
@@ -789,7 +793,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs 
                 const float dzs = dzr + S.cd0[cq];
                 const float V = fmaf(dzs, fmaf(dzs, vtxtx, 2.0f * vxtx), vxx);
                 S.u.f.WT[slot] = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
-                S.u.f.IDX[slot] = i;
+                S.u.f.IDX[slot] = (short)i;
             } else {
                 A.trk_vtx[g] = -1;
                 A.trk_w[g] = 0.0f;
@@ -800,10 +804,14 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs 
     stamp<DEBUG>(ts, 5);
 
     // fit (Sec. 3.5): L lanes per vertex, L the largest power of two with
-    // L * vertices <= lanes of the team
+    // L * vertices <= 64 for small teams (one wavefront fits them all and the
+    // others skip the fit: fewer instructions per event than spreading the
+    // vertices over the team, whose narrower groups need deeper sums, and
+    // the other teams on the CU use the freed issue slots), <= the team's
+    // lanes for large-event teams (one per CU: there latency decides)
     int lg = 6;
     {
-        const int target = NT / max(nl, 1);
+        const int target = ((!BIG && nl <= 64) ? 64 : NT) / max(nl, 1);
         while (lg > 0 && (1 << lg) > target)
             --lg;
     }
@@ -1038,15 +1046,21 @@ static hipError_t record(void *ev, hipStream_t st)
 }
 
 template <int W, int CAP, bool DEBUG>
-static hipError_t launch_pair(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
+static hipError_t launch_pair(const KArgs &args, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
-    hipError_t err = record(ev ? ev->main_begin : nullptr, st);
+    KArgs A = args;
+    if (!A.n_events_dev && A.n_events < 2)
+        A.order = nullptr;   // nothing to order
+    hipError_t err = hipSuccess;
     const int mode = (s.persistent == 1 || s.persistent == 3) ? 1 : 0;
-    if (err == hipSuccess && A.order) {
+    if (A.order) {
         hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
                            A.order);
         err = hipGetLastError();
     }
+    // the main-kernel timing brackets the fused launch alone
+    if (err == hipSuccess)
+        err = record(ev ? ev->main_begin : nullptr, st);
     if (err == hipSuccess)
         err = launch_one<W, CAP, false, DEBUG>(A, mode, s.teams_per_cu, st);
     if (err == hipSuccess)
