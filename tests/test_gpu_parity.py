@@ -262,3 +262,11 @@ def test_config3_beam_gas_sample():
 def test_config4_high_pileup_sample():
     b = synth.generate("pp_mu40_20kev", n_events=800, keep_truth=False)
     check(b, debug=True, name="mu=40 800 events")
+
+
+def test_sorted_launch_over_several_ordering_chunks():
+    """40,000 events: the ordering launch holds 16,384 events per pass, so the
+    sorted schedule's order spans three passes; every event is compared."""
+    b = synth.generate("pp_mu5_gas_50kev", n_events=40000, keep_truth=False)
+    check(b, schedule=dict(waves_per_team=2, track_capacity=512, persistent=4, teams_per_cu=0), debug=False,
+          name="pp + beam-gas 40k events, sorted")
