@@ -47,6 +47,8 @@ class OrcParams(ctypes.Structure):
         ("chi2_max", ctypes.c_double), ("conv_dchi2", ctypes.c_double), ("conv_dz", ctypes.c_double),
         ("max_rho_pp", ctypes.c_double), ("sing_ratio", ctypes.c_double),
         ("max_tracks", ctypes.c_int), ("max_vertices", ctypes.c_int),
+        ("assoc_mode", ctypes.c_int), ("chi2_max_mv", ctypes.c_double), ("chi2_window_mv", ctypes.c_double),
+        ("conv_dz_mv", ctypes.c_double), ("dup_ratio", ctypes.c_double), ("w_count_mv", ctypes.c_double),
     ]
 
 
@@ -97,6 +99,10 @@ def lib():
         L.orc_partition.argtypes = [ctypes.c_void_p, ctypes.c_int, ip, P(OrcParams)]
         L.orc_fit.argtypes = [ctypes.c_void_p * 8, ip, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, P(OrcParams), P(OrcVertex), dp]
+        L.orc_mv_weight.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_mv_weight.restype = ctypes.c_double
+        L.orc_fit_mv.argtypes = [ctypes.c_void_p * 8, ip, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, P(OrcParams), P(OrcVertex), dp]
         L.orc_find.argtypes = [ctypes.c_void_p * 8, ip, ctypes.c_int, fp, P(OrcParams), ip, ip, ctypes.c_void_p,
                                ip, dp, ip, ctypes.c_void_p, ip, fp, fp, ip, ctypes.c_int]
         L.orc_max_threads.argtypes = []
@@ -235,6 +241,32 @@ def fit(tracks: np.ndarray, seed, params=None):
     v = OrcVertex()
     bad = lib().orc_fit(arr, _ptr(idx, ctypes.c_int), n, float(seed[0]), float(seed[1]), float(seed[2]),
                         ctypes.byref(P), ctypes.byref(v), _ptr(w, ctypes.c_double))
+    rec = np.frombuffer(bytes(v), dtype=_VERTEX_DTYPE)[0]
+    del keep
+    return bool(bad), rec, w[:n].copy()
+
+
+def mv_weight(chi2: float, others: float = 0.0, chi2_max: float = 4.0) -> float:
+    """Eq. 18 for one track: chi2 relative to this candidate, the sum of
+    exp(-chi2_k / 2) over the other candidates."""
+    return lib().orc_mv_weight(float(chi2), float(others), float(chi2_max))
+
+
+def fit_mv(tracks: np.ndarray, others, seed, params=None):
+    """Fit with the weights of Eq. 18 (GPU variant) of all tracks of an (n, 8)
+    array from seed (x, y, z); others[k] is track k's sum of exp(-chi2 / 2)
+    over the other candidates.  Returns (failed, vertex record, weights)."""
+    P = make_params(params)
+    t = np.asarray(tracks, dtype=np.float32).reshape(-1, 8)
+    n = t.shape[0]
+    arr, keep = _track_ptrs([t[:, k] for k in range(8)])
+    idx = np.arange(n, dtype=np.int32)
+    oth = np.ascontiguousarray(np.broadcast_to(np.asarray(others, dtype=np.float64), (n,)))
+    w = np.zeros(max(n, 1), dtype=np.float64)
+    v = OrcVertex()
+    bad = lib().orc_fit_mv(arr, _ptr(idx, ctypes.c_int), _ptr(oth, ctypes.c_double), n, float(seed[0]),
+                           float(seed[1]), float(seed[2]), ctypes.byref(P), ctypes.byref(v),
+                           _ptr(w, ctypes.c_double))
     rec = np.frombuffer(bytes(v), dtype=_VERTEX_DTYPE)[0]
     del keep
     return bool(bad), rec, w[:n].copy()

@@ -66,6 +66,20 @@ void orc_params_default(orc_params *p)
     p->sing_ratio = 1e-4;
     p->max_tracks = 4096;
     p->max_vertices = 128;
+    /* GPU variant (Sec. 3.5, Eq. 18).  The paper gives no default for the
+       cut-off of Eq. 18; 4 is the value of its illustration, with which an
+       uncontested weight is close to the Tukey weight at 12, as the text
+       says it should be.  The chi2 pre-cut (Sec. 5) has no value either: 25
+       leaves out tracks whose uncontested weight at the seed is below 3e-5.
+       The duplicate test reads "difference over the sum of the variances
+       below 25" as dz^2 / (Czz_1 + Czz_2) < 25, i.e. closer than five
+       combined standard deviations. */
+    p->assoc_mode = ORC_ASSOC_PARTITION;
+    p->chi2_max_mv = 4.0;
+    p->chi2_window_mv = 25.0;
+    p->conv_dz_mv = 0.0005;          /* Sec. 3.5, GPU criterion: 0.5 micrometre */
+    p->dup_ratio = 25.0;
+    p->w_count_mv = 0.5;
 }
 
 int orc_nbins(const orc_params *p)
@@ -490,9 +504,23 @@ static double rel_dist(double q, double t)
  * evaluated at the final alpha, and ndof = 2 sum w - 3.  The fit fails when
  * no weight is left or the Hessian counts as singular (see inverse3).
  */
-int orc_fit(const float *const trk[8], const int *idx, int n,
-            double x_seed, double y_seed, double z_seed, const orc_params *p,
-            orc_vertex *v, double *w_out)
+/* Eq. 18 */
+double orc_mv_weight(double chi2, double others, double chi2_max)
+{
+    const double e = exp(-0.5 * chi2);
+    return e / (exp(-0.5 * chi2_max) + e + others);
+}
+
+static double fit_weight(double chi2, const double *others, int k, const orc_params *p)
+{
+    return others ? orc_mv_weight(chi2, others[k], p->chi2_max_mv) : tukey(chi2, p->chi2_max);
+}
+
+/* others == NULL: Tukey weights and the x86 criterion; otherwise the weights
+   of Eq. 18 and the GPU criterion */
+static int fit_core(const float *const trk[8], const int *idx, const double *others, int n,
+                    double x_seed, double y_seed, double z_seed, const orc_params *p,
+                    orc_vertex *v, double *w_out)
 {
     double alpha[3] = {x_seed, y_seed, z_seed};
     double hess_last[3][3];
@@ -522,7 +550,7 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
             const double H[2][3] = {{-1.0, 0.0, (double)trk[3][i]}, {0.0, -1.0, (double)trk[4][i]}};
             double r[2];
             const double chi2 = track_chi2(trk, i, W, alpha, r);
-            const double w = tukey(chi2, p->chi2_max);
+            const double w = fit_weight(chi2, others, k, p);
             sumw += w;
             /* grad += 2 w H^T W r ; hess += 2 w H^T W H  (Eq. 10-11) */
             double WH[2][3];
@@ -553,8 +581,9 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
 
         /* how close this stop/continue decision came to flipping */
         const double q1 = fabs(dchi2), q2 = fabs(d[2]);
-        const double r1 = rel_dist(q1, p->conv_dchi2), r2 = rel_dist(q2, p->conv_dz);
-        const int below1 = q1 < p->conv_dchi2, below2 = q2 < p->conv_dz;
+        const double tz = others ? p->conv_dz_mv : p->conv_dz;
+        const double r1 = others ? INFINITY : rel_dist(q1, p->conv_dchi2), r2 = rel_dist(q2, tz);
+        const int below1 = others ? 1 : q1 < p->conv_dchi2, below2 = q2 < tz;
         double frag;
         if (below1 && below2)
             frag = (r1 < r2) ? r1 : r2;
@@ -604,7 +633,7 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
         const double W[2][2] = {{Wd[k], 0.0}, {0.0, Wd[k]}};
         double r[2];
         const double chi2 = track_chi2(trk, idx[k], W, alpha, r);
-        const double w = tukey(chi2, p->chi2_max);
+        const double w = fit_weight(chi2, others, k, p);
         w_out[k] = w;
         chi2_tot += w * chi2;
         sumw += w;
@@ -628,6 +657,178 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
     return 0;
 }
 
+int orc_fit(const float *const trk[8], const int *idx, int n,
+            double x_seed, double y_seed, double z_seed, const orc_params *p,
+            orc_vertex *v, double *w_out)
+{
+    return fit_core(trk, idx, NULL, n, x_seed, y_seed, z_seed, p, v, w_out);
+}
+
+int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, int n,
+               double x_seed, double y_seed, double z_seed, const orc_params *p,
+               orc_vertex *v, double *w_out)
+{
+    return fit_core(trk, idx, others, n, x_seed, y_seed, z_seed, p, v, w_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.5 and Sec. 5, GPU variant: implicit association (Eq. 18)          */
+/* ------------------------------------------------------------------------ */
+/*
+ * Every associable track is weighted to every candidate.  Candidate j fits
+ * the tracks whose chi2 at its seed is below chi2_window_mv (the pre-cut of
+ * Sec. 5), with W_ij = 1 / Vx at its seed as in the partition fit, and the
+ * weights of Eq. 18, in which the other candidates enter at their seeds
+ * (their terms exp(-chi2_ik / 2) are summed over the candidates whose
+ * pre-cut the track passes).  Convergence is the GPU criterion |dz| <
+ * conv_dz_mv.  A vertex's track count is the number of tracks whose final
+ * weight to it is at least w_count_mv (1/2: at chi2 = chi2_max_mv an
+ * uncontested track has exactly that weight).  Duplicates: among the
+ * successful fits, taken by decreasing track count (lower z first on ties),
+ * a vertex is dropped when dz^2 / (Czz_1 + Czz_2) < dup_ratio to one already
+ * kept.  Then the selection of the partition path applies (track count,
+ * distance to the beamline in the pp region) and the kept vertices are
+ * written in z order.  Each track reports the written vertex that gives it
+ * the largest final weight (the earlier one on ties), or (-1, 0).
+ */
+static void mv_event(const float *const ev[8], int n, const float beam[4], const orc_params *p, const int *fl,
+                     orc_cluster *cl, int ncl, int a, int *n_vtx, orc_vertex *vtx, int *trk_vtx, double *trk_w)
+{
+    const int gas_bin = orc_gas_bin(p);
+    const int nn = n > 0 ? n : 1, nc = ncl > 0 ? ncl : 1;
+    double *e0 = (double *)calloc((size_t)nc * (size_t)nn, sizeof(double));   /* e0[j n + i] */
+    char *in = (char *)calloc((size_t)nc * (size_t)nn, 1);
+    int *idx = (int *)malloc(sizeof(int) * (size_t)nn);
+    double *oth = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *w = (double *)malloc(sizeof(double) * (size_t)nn);
+    double *wall = (double *)calloc((size_t)nc * (size_t)nn, sizeof(double)); /* final weights */
+    orc_vertex *cand = (orc_vertex *)calloc((size_t)nc, sizeof(orc_vertex));
+    int *ok = (int *)calloc((size_t)nc, sizeof(int));
+    int *keep = (int *)calloc((size_t)nc, sizeof(int));
+    int i, j, k;
+
+    /* pre-cut and the terms of Eq. 18 at the seeds */
+    for (j = 0; j < ncl; ++j) {
+        const double zs = cl[j].z_seed;
+        const double alpha[3] = {(double)beam[0] + (double)beam[2] * zs, (double)beam[1] + (double)beam[3] * zs, zs};
+        int m = 0;
+        for (i = 0; i < n; ++i) {
+            if (!(fl[i] & ORC_TR_ASSOC))
+                continue;
+            const double dz = zs - (double)ev[2][i];
+            const double Vx = (double)ev[5][i] + 2.0 * dz * (double)ev[6][i] + dz * dz * (double)ev[7][i];
+            if (!(Vx > 0.0 && isfinite(Vx)))
+                continue;
+            const double W[2][2] = {{1.0 / Vx, 0.0}, {0.0, 1.0 / Vx}};
+            double r[2];
+            const double chi2 = track_chi2(ev, i, W, alpha, r);
+            if (chi2 < p->chi2_window_mv) {
+                in[(size_t)j * nn + i] = 1;
+                e0[(size_t)j * nn + i] = exp(-0.5 * chi2);
+                ++m;
+            }
+        }
+        cl[j].kept = 1;
+        cl[j].n_assoc = m;
+        cl[j].own_lo = cl[j].own_hi = -1;
+    }
+
+    /* one fit per candidate */
+    for (j = 0; j < ncl; ++j) {
+        int m = 0;
+        for (i = 0; i < n; ++i) {
+            if (!in[(size_t)j * nn + i])
+                continue;
+            double o = 0.0;
+            for (k = 0; k < ncl; ++k)
+                if (k != j)
+                    o += e0[(size_t)k * nn + i];
+            idx[m] = i;
+            oth[m] = o;
+            ++m;
+        }
+        const double zs = cl[j].z_seed;
+        const double xs = (double)beam[0] + (double)beam[2] * zs;
+        const double ys = (double)beam[1] + (double)beam[3] * zs;
+        ok[j] = !orc_fit_mv(ev, idx, oth, m, xs, ys, zs, p, &cand[j], w);
+        int cnt = 0;
+        for (k = 0; k < m; ++k) {
+            wall[(size_t)j * nn + idx[k]] = w[k];
+            if (w[k] >= p->w_count_mv)
+                ++cnt;
+        }
+        cand[j].n_tracks = cnt;
+        cand[j].bin_lo = cl[j].lo;
+        cand[j].bin_hi = cl[j].hi;
+        cand[j].peak_bin = cl[j].peak;
+    }
+
+    /* duplicates: the successful fits by decreasing track count, lower z
+       first on ties; each is kept unless it duplicates one kept before it */
+    for (;;) {
+        int best = -1;
+        for (j = 0; j < ncl; ++j)   /* ok[j]: fitted and not yet decided */
+            if (ok[j] && (best < 0 || cand[j].n_tracks > cand[best].n_tracks))
+                best = j;
+        if (best < 0)
+            break;
+        int dup = 0;
+        for (k = 0; k < ncl; ++k) {
+            if (!keep[k])
+                continue;
+            const double d = cand[best].z - cand[k].z;
+            if (d * d < p->dup_ratio * (cand[best].cov[5] + cand[k].cov[5]))
+                dup = 1;
+        }
+        ok[best] = 0;
+        keep[best] = !dup;
+    }
+
+    /* selection, output in z order */
+    int *out_of = (int *)malloc(sizeof(int) * (size_t)nc);
+    for (j = 0; j < ncl; ++j) {
+        out_of[j] = -1;
+        if (!keep[j])
+            continue;
+        const int gas = cl[j].peak < gas_bin;
+        int sel = cand[j].n_tracks >= (gas ? p->pv_min_gas : p->pv_min_pp);
+        if (sel && !gas) {
+            const double bx = cand[j].x - ((double)beam[0] + (double)beam[2] * cand[j].z);
+            const double by = cand[j].y - ((double)beam[1] + (double)beam[3] * cand[j].z);
+            sel = sqrt(bx * bx + by * by) <= p->max_rho_pp;
+        }
+        if (!sel)
+            continue;
+        out_of[j] = (*n_vtx)++;
+        vtx[out_of[j]] = cand[j];
+    }
+    for (i = 0; i < n; ++i) {
+        int bv = -1;
+        double bw = 0.0;
+        for (j = 0; j < ncl; ++j) {
+            if (out_of[j] < 0 || !in[(size_t)j * nn + i])
+                continue;
+            const double wij = wall[(size_t)j * nn + i];
+            if (bv < 0 || wij > bw) {
+                bv = out_of[j];
+                bw = wij;
+            }
+        }
+        trk_vtx[a + i] = bv;
+        trk_w[a + i] = bv >= 0 ? bw : 0.0;
+    }
+    free(out_of);
+    free(e0);
+    free(in);
+    free(idx);
+    free(oth);
+    free(w);
+    free(wall);
+    free(cand);
+    free(ok);
+    free(keep);
+}
+
 /* ------------------------------------------------------------------------ */
 /* the whole path                                                           */
 /* ------------------------------------------------------------------------ */
@@ -639,7 +840,9 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
  * and, in the pp region, it lies within max_rho_pp of the beamline (end of
  * Sec. 3.5).  Regions are decided by the cluster's highest bin.  Kept
  * vertices are written in z (cluster) order; their tracks get the vertex
- * index and final weight, every other track (-1, 0).
+ * index and final weight, every other track (-1, 0).  With assoc_mode
+ * ORC_ASSOC_MULTIVERTEX the association, fit and selection are those of the
+ * GPU variant (mv_event).
  */
 static void find_event(const float *const trk[8], int a, int n, const float beam[4],
                        const orc_params *p, int nb, int *n_vtx, int *status, orc_vertex *vtx,
@@ -694,6 +897,19 @@ static void find_event(const float *const trk[8], int a, int n, const float beam
     const int ncl = orc_peak_search(h, p, cl, maxv, &overflow);
     if (overflow)
         *status |= ORC_EV_VERTEX_OVERFLOW;
+    if (p->assoc_mode == ORC_ASSOC_MULTIVERTEX) {
+        mv_event(ev, n, beam, p, fl, cl, ncl, a, n_vtx, vtx, trk_vtx, trk_w);
+        if (clusters) {
+            memcpy(clusters, cl, sizeof(orc_cluster) * (size_t)ncl);
+            *n_clusters = ncl;
+        }
+        free(cl);
+        free(h);
+        free(c);
+        free(bin);
+        free(fl);
+        return;
+    }
     orc_partition(cl, ncl, c, p);
     if (clusters) {
         memcpy(clusters, cl, sizeof(orc_cluster) * (size_t)ncl);

@@ -58,7 +58,18 @@ typedef struct {
     double sing_ratio;         /* normal matrix singular below this det / prod(diag) */
     /* capacities */
     int   max_tracks, max_vertices;
+    /* GPU variant of the association and fit (Sec. 3.5, Eq. 18, Sec. 5) */
+    int    assoc_mode;        /* 0: partition association, Tukey fit (Sec. 3.4-3.5);
+                                 1: every track weighted to every candidate (Eq. 18) */
+    double chi2_max_mv;       /* chi2 at which an uncontested weight is 1/2 (Eq. 18) */
+    double chi2_window_mv;    /* tracks enter a candidate's fit below this chi2 at its seed */
+    double conv_dz_mv;        /* GPU convergence: |dz| below this, no dchi2 requirement */
+    double dup_ratio;         /* duplicates: dz^2 / (Czz_1 + Czz_2) below this */
+    double w_count_mv;        /* a track counts for a vertex with final weight >= this */
 } orc_params;
+
+#define ORC_ASSOC_PARTITION   0
+#define ORC_ASSOC_MULTIVERTEX 1
 
 typedef struct {
     int lo, hi, peak;          /* seed cluster bin range and its first highest bin */
@@ -116,6 +127,17 @@ int  orc_partition(orc_cluster *cl, int n_cl, const int *c, const orc_params *p)
 int  orc_fit(const float *const trk[8], const int *idx, int n,
              double x_seed, double y_seed, double z_seed, const orc_params *p,
              orc_vertex *v, double *w_out);
+
+/* Eq. 18: weight of a track with chi2 relative to this candidate, when its
+   terms exp(-chi2_k / 2) for the other candidates sum to `others` */
+double orc_mv_weight(double chi2, double others, double chi2_max);
+
+/* the fit of orc_fit with the weights of Eq. 18: others[k] is the sum of
+   exp(-chi2 / 2) of track idx[k] relative to the other candidates at their
+   seeds; converged when |dz| < conv_dz_mv (the GPU criterion of Sec. 3.5) */
+int  orc_fit_mv(const float *const trk[8], const int *idx, const double *others, int n,
+                double x_seed, double y_seed, double z_seed, const orc_params *p,
+                orc_vertex *v, double *w_out);
 
 /* Whole path over a batch.  trk: 8 arrays of offsets[n_events] tracks.
    vtx: n_events * max_vertices records; trk_vtx / trk_w per input track.

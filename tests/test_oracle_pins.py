@@ -774,3 +774,211 @@ def test_fit_singular_when_one_track_keeps_weight():
     assert ratio < 1e-4
     assert oracle.fit(near, (0.0, 0.0, 5.0))[0]
     assert not oracle.fit(near, (0.0, 0.0, 5.0), {"sing_ratio": ratio / 2})[0]
+
+
+# --------------------------------------------------------------------------
+# GPU variant: implicit association with the weights of Eq. 18
+# --------------------------------------------------------------------------
+def test_eq18_uncontested_weight_is_half_at_the_cutoff():
+    """Sec. 3.5: chi2_max is the chi2 at which the weight of a track with no
+    competing vertex is 1/2; without competitors the weight is a logistic
+    function of chi2 - chi2_max with scale 2, so it is 1/4 two ln 3 above it
+    and 3/4 two ln 3 below it, and it falls monotonically."""
+    for cmax in (1.0, 4.0, 12.0, 30.0):
+        assert oracle.mv_weight(cmax, 0.0, cmax) == pytest.approx(0.5, abs=1e-15)
+        assert oracle.mv_weight(cmax + 2 * math.log(3), 0.0, cmax) == pytest.approx(0.25, abs=1e-14)
+        assert oracle.mv_weight(cmax - 2 * math.log(3), 0.0, cmax) == pytest.approx(0.75, abs=1e-14)
+    ws = [oracle.mv_weight(c, 0.0, 4.0) for c in np.linspace(0, 40, 81)]
+    assert all(a > b for a, b in zip(ws, ws[1:]))
+
+
+def test_eq18_weights_partition_unity_with_the_outlier_class():
+    """For one track and several candidates, the weights of Eq. 18 (each with
+    the others' terms as competitors) and the outlier share exp(-chi2_max/2)
+    / (exp(-chi2_max/2) + sum_k exp(-chi2_k/2)) add up to one; equal chi2 give
+    equal weights, and a competitor lowers a weight."""
+    rng = np.random.default_rng(40)
+    for _ in range(200):
+        m = int(rng.integers(1, 6))
+        chi2 = rng.uniform(0, 30, m)
+        e = np.exp(-0.5 * chi2)
+        ws = [oracle.mv_weight(chi2[j], float(e.sum() - e[j]), 4.0) for j in range(m)]
+        outlier = math.exp(-2.0) / (math.exp(-2.0) + e.sum())
+        assert sum(ws) + outlier == pytest.approx(1.0, abs=1e-14)
+    w_alone = oracle.mv_weight(3.0, 0.0, 4.0)
+    w_twin = oracle.mv_weight(3.0, math.exp(-1.5), 4.0)
+    assert w_twin < w_alone
+    assert oracle.mv_weight(3.0, math.exp(-4.5), 4.0) > w_twin   # a farther competitor (chi2 9) takes less
+
+
+def test_mv_fit_noise_free_vertex_is_exact():
+    """Tracks exactly through P fit back to P; every chi2 is 0 at P, so every
+    uncontested weight is 1 / (1 + exp(-chi2_max / 2))."""
+    rng = np.random.default_rng(41)
+    P = (0.125, -0.0625, 10.5)
+    t = _exact_tracks_through(P, 12, rng)
+    bad, v, w = oracle.fit_mv(t, 0.0, (0.0, 0.0, 10.5 + 0.3))
+    assert not bad
+    assert abs(v["x"] - P[0]) < 1e-9 and abs(v["y"] - P[1]) < 1e-9 and abs(v["z"] - P[2]) < 1e-9
+    assert np.allclose(w, 1.0 / (1.0 + math.exp(-2.0)), atol=1e-12)
+    assert v["ndof"] == pytest.approx(2 * 12 / (1.0 + math.exp(-2.0)) - 3)
+
+
+def test_mv_fit_is_a_fixed_point_of_weighted_least_squares():
+    """At convergence the position solves the weighted least-squares problem
+    with the final weights frozen (Eq. 10-13 with w_i from Eq. 18): solved
+    independently with numpy on whitened rows; competitors only rescale the
+    weights, and the stop rule is |dz| < 0.5 um (Sec. 3.5, GPU)."""
+    rng = np.random.default_rng(42)
+    for trial in range(40):
+        n = int(rng.integers(6, 40))
+        t = np.zeros((n, 8))
+        t[:, 3:5] = rng.normal(0, 0.3, (n, 2))
+        t[:, 2] = rng.uniform(-3, 3, n) + 7.0
+        t[:, 0:2] = rng.normal(0, 0.03, (n, 2)) + t[:, 3:5] * (t[:, 2:3] - 7.05)
+        t[:, 5] = rng.uniform(1e-4, 2.5e-3, n)
+        t = t.astype(np.float32).astype(np.float64)
+        others = rng.choice([0.0, 0.0, 0.05, 0.3], n)
+        seed = (0.0, 0.0, 7.1)
+        bad, v, w = oracle.fit_mv(t, others, seed)
+        assert not bad
+        if not (v["flags"] == 0):
+            continue
+        dz = seed[2] - t[:, 2]
+        sw = np.sqrt(w / (t[:, 5] + 2 * dz * t[:, 6] + dz * dz * t[:, 7]))
+        A = np.zeros((2 * n, 3))
+        y = np.zeros(2 * n)
+        A[0::2, 0] = -1
+        A[0::2, 2] = t[:, 3]
+        A[1::2, 1] = -1
+        A[1::2, 2] = t[:, 4]
+        y[0::2] = -(t[:, 0] - t[:, 2] * t[:, 3])
+        y[1::2] = -(t[:, 1] - t[:, 2] * t[:, 4])
+        sol = np.linalg.lstsq(A * np.repeat(sw, 2)[:, None], y * np.repeat(sw, 2), rcond=None)[0]
+        assert abs(sol[2] - v["z"]) < 2e-3 and abs(sol[0] - v["x"]) < 2e-3
+        # Eq. 18 weights at the final position
+        rx = t[:, 0] + (v["z"] - t[:, 2]) * t[:, 3] - v["x"]
+        ry = t[:, 1] + (v["z"] - t[:, 2]) * t[:, 4] - v["y"]
+        chi2 = (rx * rx + ry * ry) / (t[:, 5] + 2 * dz * t[:, 6] + dz * dz * t[:, 7])
+        ew = np.exp(-0.5 * chi2)
+        assert np.allclose(w, ew / (math.exp(-2.0) + ew + others), atol=1e-12)
+
+
+def test_mv_fit_stops_on_dz_alone():
+    """The GPU criterion has no dchi2 requirement: with a huge dz threshold
+    every fit stops after its first step, with a tiny one after max_iter."""
+    b = synth.generate("pp_mu5_100ev", n_events=10)
+    r = oracle.find(b, {"assoc_mode": 1, "conv_dz_mv": 1e9})
+    n = r.n_vertices
+    its = np.concatenate([r.vertices[e, :n[e]]["n_iter"] for e in range(b.n_events)])
+    assert len(its) > 20 and np.all(its == 1)
+    r = oracle.find(b, {"assoc_mode": 1, "conv_dz_mv": 0.0})
+    flags = np.concatenate([r.vertices[e, :r.n_vertices[e]]["flags"] for e in range(b.n_events)])
+    its = np.concatenate([r.vertices[e, :r.n_vertices[e]]["n_iter"] for e in range(b.n_events)])
+    assert np.all(its == 10) and np.all(flags & oracle.VX_NOT_CONVERGED)
+
+
+def test_mv_noise_free_event_finds_vertices():
+    """Three exact vertices far apart: each candidate's pre-cut holds its own
+    25 tracks only, the fits are exact, every track counts (weight 0.88 >=
+    1/2) and reports its own vertex."""
+    rng = np.random.default_rng(43)
+    Ps = [(0.01, -0.01, -40.0), (0.0, 0.02, 12.0), (-0.02, 0.0, 60.0)]
+    rows = np.concatenate([_exact_tracks_through(P, 25, rng) for P in Ps]).astype(np.float32).astype(np.float64)
+    b = synth.from_tracks([rows])
+    r = oracle.find(b, {"assoc_mode": 1}, debug=True)
+    assert r.n_vertices[0] == 3
+    assert list(r.clusters[0, :3]["n_assoc"]) == [25, 25, 25]
+    for k, P in enumerate(Ps):
+        v = r.vertices[0, k]
+        assert abs(v["z"] - P[2]) < 1e-6 and abs(v["x"] - P[0]) < 1e-6 and v["n_tracks"] == 25
+    assert np.array_equal(r.track_vertex, np.repeat([0, 1, 2], 25))
+    assert np.allclose(r.track_weight, 1.0 / (1.0 + math.exp(-2.0)), atol=1e-9)
+
+
+def test_mv_precut_bounds_the_candidate_track_lists():
+    """With a pre-cut of zero no track enters any fit, so nothing survives;
+    with an unbounded one every associable track enters every candidate."""
+    b = synth.generate("pp_mu5_100ev", n_events=10)
+    r = oracle.find(b, {"assoc_mode": 1, "chi2_window_mv": 0.0}, debug=True)
+    assert r.n_vertices.sum() == 0 and np.all(r.track_vertex == -1)
+    r = oracle.find(b, {"assoc_mode": 1, "chi2_window_mv": 1e300}, debug=True)
+    for e in range(b.n_events):
+        n_assoc = int(np.sum((r.bin[b.offsets[e]:b.offsets[e + 1]] >= 0)))
+        cl = r.clusters[e, :r.n_clusters[e]]
+        assert np.all(cl["n_assoc"] == n_assoc)
+
+
+def test_mv_duplicate_rejection_is_the_greedy_rule():
+    """Brute force on the candidates: with the selection opened up and no
+    duplicate test, every successful fit is written; with the test, the kept
+    set must be what the greedy rule (decreasing track count, lower z first,
+    drop a candidate within dz^2 < R (Czz_1 + Czz_2) of one kept before)
+    keeps from that list."""
+    b = synth.generate("pp_mu40_20kev", n_events=30)
+    loose = {"assoc_mode": 1, "pv_min_pp": 0, "pv_min_gas": 0, "max_rho_pp": 1e9}
+    r0 = oracle.find(b, dict(loose, dup_ratio=0.0))
+    checked = dropped = 0
+    for R in (25.0, 400.0, 1e6):
+        r1 = oracle.find(b, dict(loose, dup_ratio=R))
+        for e in range(b.n_events):
+            c = r0.vertices[e, :r0.n_vertices[e]]
+            order = sorted(range(len(c)), key=lambda k: (-c[k]["n_tracks"], k))
+            kept = []
+            for k in order:
+                if all((c[k]["z"] - c[q]["z"]) ** 2 >= R * (c[k]["cov"][5] + c[q]["cov"][5]) for q in kept):
+                    kept.append(k)
+            want = c[sorted(kept)]
+            got = r1.vertices[e, :r1.n_vertices[e]]
+            assert len(got) == len(want)
+            assert np.array_equal(got["z"], want["z"]) and np.array_equal(got["n_tracks"], want["n_tracks"])
+            checked += 1
+            dropped += len(c) - len(kept)
+    assert checked == 90 and dropped > 30
+
+
+def test_mv_track_reports_its_largest_weight():
+    """Recomputed from the written vertices (selection opened up, so that in
+    events where every cluster gives a vertex all candidates are visible):
+    pre-cut at each seed, the terms of Eq. 18 at the seeds, final weights at
+    the fitted positions; each track must report the vertex with the largest
+    weight, that weight, and each vertex's track count the tracks at >= 1/2."""
+    b = synth.generate("pp_mu5_100ev", n_events=40)
+    p = oracle.default_params()
+    r = oracle.find(b, {"assoc_mode": 1, "pv_min_pp": 0, "pv_min_gas": 0, "max_rho_pp": 1e9,
+                        "dup_ratio": 0.0}, debug=True)
+    t = np.stack(b.fields(), axis=1).astype(np.float64)
+    events = 0
+    for e in range(b.n_events):
+        nv = r.n_vertices[e]
+        if nv != r.n_clusters[e] or nv == 0:
+            continue
+        events += 1
+        a0, a1 = b.offsets[e], b.offsets[e + 1]
+        tr = t[a0:a1]
+        ok = r.bin[a0:a1] >= 0
+        vs = r.vertices[e, :nv]
+        zs = vs["z_seed"]
+        dzs = zs[:, None] - tr[None, :, 2]
+        Vx = tr[None, :, 5] + 2 * dzs * tr[None, :, 6] + dzs * dzs * tr[None, :, 7]
+        W = np.where(Vx > 0, 1 / Vx, 0)
+
+        def chi2_at(x, y, z):
+            rx = tr[None, :, 0] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 3] - x[:, None]
+            ry = tr[None, :, 1] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 4] - y[:, None]
+            return W * (rx * rx + ry * ry)
+        c0 = chi2_at(np.zeros(nv), np.zeros(nv), zs)       # the batches' beamline is at x = y = 0
+        inw = (c0 < p["chi2_window_mv"]) & (W > 0) & ok[None, :]
+        e0 = np.where(inw, np.exp(-0.5 * c0), 0.0)
+        others = e0.sum(0)[None, :] - e0
+        cf = chi2_at(vs["x"], vs["y"], vs["z"])
+        ef = np.exp(-0.5 * cf)
+        w = np.where(inw, ef / (math.exp(-0.5 * p["chi2_max_mv"]) + ef + others), -1.0)
+        assert np.array_equal(vs["n_tracks"], np.sum(inw & (w >= 0.5), axis=1))
+        for i in range(a1 - a0):
+            if not inw[:, i].any():
+                assert r.track_vertex[a0 + i] == -1
+                continue
+            assert r.track_vertex[a0 + i] == int(np.argmax(w[:, i]))
+            assert r.track_weight[a0 + i] == pytest.approx(w[:, i].max(), abs=1e-9)
+    assert events >= 20
