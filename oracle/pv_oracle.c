@@ -677,7 +677,9 @@ int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, 
 /*
  * Every associable track is weighted to every candidate.  Candidate j fits
  * the tracks whose chi2 at its seed is below chi2_window_mv (the pre-cut of
- * Sec. 5), with W_ij = 1 / Vx at its seed as in the partition fit, and the
+ * Sec. 5, in binary32 as below; the lists of all candidates together hold at
+ * most max_tracks entries, else the event is flagged as too large), with
+ * W_ij = 1 / Vx at its seed as in the partition fit, and the
  * weights of Eq. 18, in which the other candidates enter at their seeds
  * (their terms exp(-chi2_ik / 2) are summed over the candidates whose
  * pre-cut the track passes).  Convergence is the GPU criterion |dz| <
@@ -691,8 +693,48 @@ int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, 
  * written in z order.  Each track reports the written vertex that gives it
  * the largest final weight (the earlier one on ties), or (-1, 0).
  */
+/*
+ * The pre-cut decides which tracks enter a fit, an integer decision, so it is
+ * defined in binary32 with the operations written out (as the projection):
+ * frame at the beamline point of the candidate's peak-bin centre
+ * z_i = z_min + (i + 1/2) dz, seed offset d0 = delta dz (Eq. 4-5, delta from
+ * the bin contents converted to binary32), track position at z_i relative to
+ * that point, V_x of Eq. 2 at the seed, residual at the seed (Eq. 9) and
+ * chi2 = W (rx^2 + ry^2) (Eq. 7); fmaf is the fused multiply-add.  The chi2
+ * is also the one whose exp(-chi2 / 2) enters Eq. 18 for the other
+ * candidates.  Returns W (0: unusable track) and the chi2.
+ */
+static float mv_seed_offset(const int *h, int nb, int i, const orc_params *p)
+{
+    const int Ni = h[i];
+    const int Nm = (i > 0) ? h[i - 1] : 0;
+    const int Np = (i + 1 < nb) ? h[i + 1] : 0;
+    const int den = 2 * Ni - Np - Nm;
+    float delta = (den > 0) ? (0.5f * (float)(Np - Nm)) / (float)den : 0.0f;
+    if (delta < -0.5f)
+        delta = -0.5f;
+    if (delta > 0.5f)
+        delta = 0.5f;
+    return delta * p->dz;
+}
+
+static float mv_precut_chi2(const float *const ev[8], int i, const float beam[4], float zr, float d0, float *W)
+{
+    const float x = ev[0][i], y = ev[1][i], z = ev[2][i], tx = ev[3][i], ty = ev[4][i];
+    const float dzr = zr - z;
+    const float X = fmaf(dzr, tx, x) - (beam[0] + beam[2] * zr);
+    const float Y = fmaf(dzr, ty, y) - (beam[1] + beam[3] * zr);
+    const float dzs = dzr + d0;
+    const float V = fmaf(dzs, fmaf(dzs, ev[7][i], 2.0f * ev[6][i]), ev[5][i]);
+    *W = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
+    const float rx = fmaf(d0, tx, X) - beam[2] * d0;
+    const float ry = fmaf(d0, ty, Y) - beam[3] * d0;
+    return *W * fmaf(rx, rx, ry * ry);
+}
+
 static void mv_event(const float *const ev[8], int n, const float beam[4], const orc_params *p, const int *fl,
-                     orc_cluster *cl, int ncl, int a, int *n_vtx, orc_vertex *vtx, int *trk_vtx, double *trk_w)
+                     const int *h, int nb, orc_cluster *cl, int ncl, int a, int *status, int *n_vtx,
+                     orc_vertex *vtx, int *trk_vtx, double *trk_w)
 {
     const int gas_bin = orc_gas_bin(p);
     const int nn = n > 0 ? n : 1, nc = ncl > 0 ? ncl : 1;
@@ -708,29 +750,31 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
     int i, j, k;
 
     /* pre-cut and the terms of Eq. 18 at the seeds */
+    long total = 0;
     for (j = 0; j < ncl; ++j) {
-        const double zs = cl[j].z_seed;
-        const double alpha[3] = {(double)beam[0] + (double)beam[2] * zs, (double)beam[1] + (double)beam[3] * zs, zs};
+        const float zr = p->z_min + ((float)cl[j].peak + 0.5f) * p->dz;
+        const float d0 = mv_seed_offset(h, nb, cl[j].peak, p);
         int m = 0;
         for (i = 0; i < n; ++i) {
             if (!(fl[i] & ORC_TR_ASSOC))
                 continue;
-            const double dz = zs - (double)ev[2][i];
-            const double Vx = (double)ev[5][i] + 2.0 * dz * (double)ev[6][i] + dz * dz * (double)ev[7][i];
-            if (!(Vx > 0.0 && isfinite(Vx)))
-                continue;
-            const double W[2][2] = {{1.0 / Vx, 0.0}, {0.0, 1.0 / Vx}};
-            double r[2];
-            const double chi2 = track_chi2(ev, i, W, alpha, r);
-            if (chi2 < p->chi2_window_mv) {
+            float W;
+            const float chi2 = mv_precut_chi2(ev, i, beam, zr, d0, &W);
+            if (W > 0.0f && (double)chi2 < p->chi2_window_mv) {
                 in[(size_t)j * nn + i] = 1;
-                e0[(size_t)j * nn + i] = exp(-0.5 * chi2);
+                e0[(size_t)j * nn + i] = exp(-0.5 * (double)chi2);
                 ++m;
             }
         }
         cl[j].kept = 1;
         cl[j].n_assoc = m;
         cl[j].own_lo = cl[j].own_hi = -1;
+        total += m;
+    }
+    /* the candidates' track lists share the event's track capacity */
+    if (total > p->max_tracks) {
+        *status |= ORC_EV_TOO_MANY_TRACKS;
+        ncl = 0;
     }
 
     /* one fit per candidate */
@@ -898,7 +942,7 @@ static void find_event(const float *const trk[8], int a, int n, const float beam
     if (overflow)
         *status |= ORC_EV_VERTEX_OVERFLOW;
     if (p->assoc_mode == ORC_ASSOC_MULTIVERTEX) {
-        mv_event(ev, n, beam, p, fl, cl, ncl, a, n_vtx, vtx, trk_vtx, trk_w);
+        mv_event(ev, n, beam, p, fl, h, nb, cl, ncl, a, status, n_vtx, vtx, trk_vtx, trk_w);
         if (clusters) {
             memcpy(clusters, cl, sizeof(orc_cluster) * (size_t)ncl);
             *n_clusters = ncl;

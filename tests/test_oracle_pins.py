@@ -953,7 +953,6 @@ def test_mv_track_reports_its_largest_weight():
         nv = r.n_vertices[e]
         if nv != r.n_clusters[e] or nv == 0:
             continue
-        events += 1
         a0, a1 = b.offsets[e], b.offsets[e + 1]
         tr = t[a0:a1]
         ok = r.bin[a0:a1] >= 0
@@ -967,18 +966,46 @@ def test_mv_track_reports_its_largest_weight():
             rx = tr[None, :, 0] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 3] - x[:, None]
             ry = tr[None, :, 1] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 4] - y[:, None]
             return W * (rx * rx + ry * ry)
+        # the oracle takes the pre-cut in binary32 (an integer decision): here in
+        # binary64, so pairs within 1e-4 of the cut are left undecided
         c0 = chi2_at(np.zeros(nv), np.zeros(nv), zs)       # the batches' beamline is at x = y = 0
+        amb = np.abs(c0 - p["chi2_window_mv"]) < 1e-4 * p["chi2_window_mv"]
+        if np.any(amb & (W > 0) & ok[None, :]):
+            continue
+        events += 1
         inw = (c0 < p["chi2_window_mv"]) & (W > 0) & ok[None, :]
         e0 = np.where(inw, np.exp(-0.5 * c0), 0.0)
         others = e0.sum(0)[None, :] - e0
         cf = chi2_at(vs["x"], vs["y"], vs["z"])
         ef = np.exp(-0.5 * cf)
         w = np.where(inw, ef / (math.exp(-0.5 * p["chi2_max_mv"]) + ef + others), -1.0)
-        assert np.array_equal(vs["n_tracks"], np.sum(inw & (w >= 0.5), axis=1))
+        near = inw & (np.abs(w - 0.5) < 1e-6)
+        assert np.all(np.abs(vs["n_tracks"] - np.sum(inw & (w >= 0.5), axis=1)) <= np.sum(near, axis=1))
+        assert list(r.clusters[e, :nv]["n_assoc"]) == list(np.sum(inw, axis=1))
         for i in range(a1 - a0):
             if not inw[:, i].any():
                 assert r.track_vertex[a0 + i] == -1
                 continue
+            ws = np.sort(w[:, i])
+            if len(ws) > 1 and ws[-1] - ws[-2] < 1e-6:
+                continue
             assert r.track_vertex[a0 + i] == int(np.argmax(w[:, i]))
-            assert r.track_weight[a0 + i] == pytest.approx(w[:, i].max(), abs=1e-9)
+            assert r.track_weight[a0 + i] == pytest.approx(w[:, i].max(), abs=1e-6)
     assert events >= 20
+
+
+def test_mv_candidate_lists_share_the_track_capacity():
+    """The candidates' track lists together hold at most max_tracks entries:
+    an unbounded pre-cut puts every associable track in every list, so an
+    event with k clusters and m such tracks needs k * m entries."""
+    b = synth.generate("pp_mu5_100ev", n_events=10)
+    r = oracle.find(b, {"assoc_mode": 1, "chi2_window_mv": 1e300}, debug=True)
+    for e in range(b.n_events):
+        m = int(np.sum(r.bin[b.offsets[e]:b.offsets[e + 1]] >= 0))
+        k = int(r.n_clusters[e])
+        for cap, flagged in ((k * m, False), (k * m - 1, True)):
+            if k == 0 or cap < b.offsets[e + 1] - b.offsets[e]:
+                continue
+            r2 = oracle.find(b.select([e]), {"assoc_mode": 1, "chi2_window_mv": 1e300, "max_tracks": cap})
+            assert bool(r2.status[0] & oracle.EV_TOO_MANY_TRACKS) == flagged
+            assert (r2.n_vertices[0] == 0) or not flagged
