@@ -100,7 +100,27 @@ typedef struct {
                                           (e.g. a single weighted track)               */
     int32_t max_tracks_per_event;      /* <= 4096                                      */
     int32_t max_vertices_per_event;    /* <= 128; output slots per event               */
+    /* Association and fit variant.  PV_ASSOC_PARTITION (default): each track
+     * goes to the candidate owning its bin (Sec. 3.4), Tukey-weighted fit
+     * (Eq. 17), the x86 convergence criterion.  PV_ASSOC_MULTIVERTEX: the GPU
+     * variant of Sec. 3.5 and Sec. 5, every track weighted to every candidate
+     * with Eq. 18, the other candidates held at their seeds; a candidate fits
+     * the tracks whose chi2 at its seed (in binary32) is below chi2_window_mv;
+     * converged when |dz| < conv_dz_mv; duplicates (dz^2 / (Czz_1 + Czz_2) <
+     * dup_ratio) lose the one with fewer tracks; a vertex's n_tracks counts
+     * the tracks with final weight >= w_count_mv; all candidates' track lists
+     * together hold at most max_tracks_per_event entries (else the event is
+     * flagged PV_EV_TOO_MANY_TRACKS).                                           */
+    int32_t assoc_mode;
+    float   chi2_max_mv;               /* Eq. 18 cut-off: uncontested weight 1/2 here  */
+    float   chi2_window_mv;            /* pre-cut at the seed                          */
+    float   conv_dz_mv;                /* mm                                           */
+    float   dup_ratio;
+    float   w_count_mv;
 } pv_params;
+
+#define PV_ASSOC_PARTITION   0
+#define PV_ASSOC_MULTIVERTEX 1
 
 /* One fitted vertex, 64 bytes. */
 typedef struct {
@@ -109,7 +129,8 @@ typedef struct {
     float   chi2;                      /* sum_i w_i chi2_i at the final position      */
     float   ndof;                      /* 2 sum_i w_i - 3                              */
     float   z_seed;                    /* Eq. 4                                        */
-    int32_t n_tracks;                  /* tracks associated through the partition     */
+    int32_t n_tracks;                  /* tracks associated through the partition;
+                                          multi-vertex: tracks of weight >= w_count_mv */
     int16_t bin_lo, bin_hi;            /* seed cluster bin range                      */
     int16_t peak_bin;                  /* highest bin of the seed cluster             */
     uint8_t n_iter;                    /* fit iterations                               */
@@ -126,7 +147,8 @@ typedef struct {
 } pv_vertices_out;
 
 /* Per input track: index of its vertex within the event (-1 if none) and its
- * final Tukey weight (0 if none). */
+ * final weight (0 if none).  Multi-vertex: the written vertex that gives the
+ * track its largest weight (the earlier one when equal to 2^-16). */
 typedef struct {
     int32_t *vertex;
     float   *weight;
@@ -137,8 +159,10 @@ typedef struct {
     int32_t lo, hi, peak;              /* bin range and first highest bin              */
     float   z_seed;
     int32_t kept;                      /* 1 if it survived the association step        */
-    int32_t n_assoc;                   /* its tracks after the association step        */
-    int32_t own_lo, own_hi;            /* bins it owns after the association step      */
+    int32_t n_assoc;                   /* its tracks after the association step
+                                          (multi-vertex: tracks passing its pre-cut)   */
+    int32_t own_lo, own_hi;            /* bins it owns after the association step
+                                          (multi-vertex: -1)                           */
 } pv_cluster;
 
 /* Optional intermediate results of pv_find_debug; any member may be NULL. */

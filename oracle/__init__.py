@@ -63,14 +63,15 @@ class OrcVertex(ctypes.Structure):
                 ("cov", ctypes.c_double * 6), ("chi2", ctypes.c_double), ("ndof", ctypes.c_double),
                 ("z_seed", ctypes.c_double), ("conv_margin", ctypes.c_double), ("dchi2", ctypes.c_double),
                 ("n_tracks", ctypes.c_int), ("bin_lo", ctypes.c_int), ("bin_hi", ctypes.c_int),
-                ("peak_bin", ctypes.c_int), ("n_iter", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("peak_bin", ctypes.c_int), ("n_iter", ctypes.c_int), ("flags", ctypes.c_int),
+                ("n_near", ctypes.c_int), ("dup_margin", ctypes.c_double)]
 
 
 _VERTEX_DTYPE = np.dtype([("x", "f8"), ("y", "f8"), ("z", "f8"), ("cov", "f8", (6,)), ("chi2", "f8"),
                           ("ndof", "f8"), ("z_seed", "f8"), ("conv_margin", "f8"), ("dchi2", "f8"),
                           ("n_tracks", "i4"),
                           ("bin_lo", "i4"), ("bin_hi", "i4"), ("peak_bin", "i4"), ("n_iter", "i4"),
-                          ("flags", "i4")], align=True)
+                          ("flags", "i4"), ("n_near", "i4"), ("dup_margin", "f8")], align=True)
 _CLUSTER_DTYPE = np.dtype([("lo", "i4"), ("hi", "i4"), ("peak", "i4"), ("z_seed", "f8"), ("kept", "i4"),
                            ("n_assoc", "i4"), ("own_lo", "i4"), ("own_hi", "i4")], align=True)
 assert _VERTEX_DTYPE.itemsize == ctypes.sizeof(OrcVertex)

@@ -795,13 +795,17 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
         const double xs = (double)beam[0] + (double)beam[2] * zs;
         const double ys = (double)beam[1] + (double)beam[3] * zs;
         ok[j] = !orc_fit_mv(ev, idx, oth, m, xs, ys, zs, p, &cand[j], w);
-        int cnt = 0;
+        int cnt = 0, near = 0;
         for (k = 0; k < m; ++k) {
             wall[(size_t)j * nn + idx[k]] = w[k];
             if (w[k] >= p->w_count_mv)
                 ++cnt;
+            if (fabs(w[k] - p->w_count_mv) < 1e-4)
+                ++near;
         }
         cand[j].n_tracks = cnt;
+        cand[j].n_near = near;
+        cand[j].dup_margin = INFINITY;
         cand[j].bin_lo = cl[j].lo;
         cand[j].bin_hi = cl[j].hi;
         cand[j].peak_bin = cl[j].peak;
@@ -821,8 +825,14 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
             if (!keep[k])
                 continue;
             const double d = cand[best].z - cand[k].z;
-            if (d * d < p->dup_ratio * (cand[best].cov[5] + cand[k].cov[5]))
+            const double lim = p->dup_ratio * (cand[best].cov[5] + cand[k].cov[5]);
+            if (d * d < lim)
                 dup = 1;
+            const double mg = lim > 0.0 ? fabs(d * d / lim - 1.0) : INFINITY;
+            if (mg < cand[best].dup_margin)
+                cand[best].dup_margin = mg;
+            if (mg < cand[k].dup_margin)
+                cand[k].dup_margin = mg;
         }
         ok[best] = 0;
         keep[best] = !dup;

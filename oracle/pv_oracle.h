@@ -87,6 +87,12 @@ typedef struct {
                                   decision quantity from its threshold      */
     double dchi2;              /* predicted chi2 change of the last step (Eq. 16) */
     int n_tracks, bin_lo, bin_hi, peak_bin, n_iter, flags;
+    /* multi-vertex decisions a binary32 evaluation may take the other way:
+       tracks whose final weight is within 1e-4 of w_count_mv, and the
+       smallest |dz^2 / (R (Czz_1 + Czz_2)) - 1| of a duplicate test this
+       vertex took part in (INFINITY if none) */
+    int n_near;
+    double dup_margin;
 } orc_vertex;
 
 void orc_params_default(orc_params *p);

@@ -140,6 +140,14 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
         return fail(PV_EINVAL, "params: max_tracks_per_event must be in [0, %d]", pvk::kMaxTracks);
     if (p->max_vertices_per_event < 1 || p->max_vertices_per_event > pvk::kMaxVertices)
         return fail(PV_EINVAL, "params: max_vertices_per_event must be in [1, %d]", pvk::kMaxVertices);
+    if (p->assoc_mode != PV_ASSOC_PARTITION && p->assoc_mode != PV_ASSOC_MULTIVERTEX)
+        return fail(PV_EINVAL, "params: assoc_mode must be PV_ASSOC_PARTITION or PV_ASSOC_MULTIVERTEX");
+    if (p->assoc_mode == PV_ASSOC_MULTIVERTEX &&
+        (!(p->chi2_max_mv > 0.0f) || !(p->chi2_max_mv < 170.0f) || !(p->chi2_window_mv >= 0.0f) ||
+         !(p->conv_dz_mv > 0.0f) || !(p->dup_ratio >= 0.0f) || !std::isfinite(p->dup_ratio) ||
+         !(p->w_count_mv >= 0.0f) || !(p->w_count_mv <= 1.0f)))
+        return fail(PV_EINVAL, "params: chi2_max_mv in (0, 170), chi2_window_mv >= 0, conv_dz_mv > 0, finite "
+                               "dup_ratio >= 0 and w_count_mv in [0, 1] required");
     if (!std::isfinite(bl->x) || !std::isfinite(bl->y) || !std::isfinite(bl->tx) || !std::isfinite(bl->ty))
         return fail(PV_EINVAL, "beamline: non-finite value");
     k.z_min = p->z_min;
@@ -175,6 +183,12 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
     k.by = bl->y;
     k.btx = bl->tx;
     k.bty = bl->ty;
+    k.mv = p->assoc_mode == PV_ASSOC_MULTIVERTEX ? 1 : 0;
+    k.e_max_mv = (float)std::exp(-0.5 * (double)p->chi2_max_mv);
+    k.chi2_window_mv = p->chi2_window_mv;
+    k.conv_dz_mv = p->conv_dz_mv;
+    k.dup_ratio = p->dup_ratio;
+    k.w_count_mv = p->w_count_mv;
     return PV_OK;
 }
 
@@ -356,6 +370,17 @@ void pv_params_default(pv_params *p)
     p->sing_ratio = 1.0e-4f;       // normal matrix singular below det / prod(diag) = 1e-4
     p->max_tracks_per_event = pvk::kMaxTracks;
     p->max_vertices_per_event = pvk::kMaxVertices;
+    // GPU variant (Sec. 3.5, Sec. 5).  The paper's illustration of Eq. 18 uses
+    // a cut-off of 4, with which an uncontested weight follows the Tukey weight
+    // at 12 as the text says; it gives no value for the chi2 pre-cut (25
+    // leaves out tracks of uncontested weight below 3e-5 at the seed); the
+    // duplicate test reads as dz^2 / (Czz_1 + Czz_2) < 25.
+    p->assoc_mode = PV_ASSOC_PARTITION;
+    p->chi2_max_mv = 4.0f;
+    p->chi2_window_mv = 25.0f;
+    p->conv_dz_mv = 0.0005f;       // Sec. 3.5, GPU criterion: 0.5 micrometre
+    p->dup_ratio = 25.0f;
+    p->w_count_mv = 0.5f;
 }
 
 int32_t pv_nbins(const pv_params *p)

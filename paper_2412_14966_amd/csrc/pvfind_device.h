@@ -499,6 +499,57 @@ __device__ __forceinline__ void accumulate(FitSums &a, float X, float Y, float t
     a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
 }
 
+// Eq. 18 weight for a track of chi2 relative to this candidate, whose terms
+// for the other candidates (at their seeds) sum to `oth`; e_max =
+// exp(-chi2_max / 2).  No cut: far tracks fade out smoothly.
+__device__ __forceinline__ float mv_weight(float chi2, float oth, const KParams &p)
+{
+    const float ex = __expf(-0.5f * chi2);
+    return ex * __builtin_amdgcn_rcpf(p.e_max_mv + ex + oth);
+}
+
+__device__ __forceinline__ void accumulate_mv(FitSums &a, float X, float Y, float tx, float ty, float wt, float oth,
+                                              float dx, float dy, float dz, const KParams &p)
+{
+    const float rx = fmaf(dz, tx, X) - dx;
+    const float ry = fmaf(dz, ty, Y) - dy;
+    const float chi2 = wt * fmaf(rx, rx, ry * ry);
+    const float ww = mv_weight(chi2, oth, p) * wt;
+    a.s0 += ww;
+    a.sx = fmaf(ww, tx, a.sx);
+    a.sy = fmaf(ww, ty, a.sy);
+    a.szz = fmaf(ww, fmaf(tx, tx, ty * ty), a.szz);
+    const float px = ww * rx, py = ww * ry;
+    a.gx += px;
+    a.gy += py;
+    a.gz = fmaf(px, tx, fmaf(py, ty, a.gz));
+}
+
+// Multi-vertex pre-cut (Sec. 5) of a track for the candidate whose peak-bin
+// centre is zr and seed offset d0: the track's fit frame values (position at
+// zr relative to the beamline point there, 1 / V_x of Eq. 2 at the seed) and
+// its chi2 at the seed (Eq. 7, Eq. 9).  Written out in binary32 with explicit
+// fused multiply-adds: the pre-cut is an integer decision.
+struct MvPre {
+    float X, Y, WT, chi2;
+};
+
+__device__ __forceinline__ MvPre mv_precut(const float t[8], float zr, float d0, const KParams &p)
+{
+    const float x = t[0], y = t[1], z = t[2], tx = t[3], ty = t[4];
+    const float dzr = zr - z;
+    MvPre m;
+    m.X = fmaf(dzr, tx, x) - (p.bx + p.btx * zr);
+    m.Y = fmaf(dzr, ty, y) - (p.by + p.bty * zr);
+    const float dzs = dzr + d0;
+    const float V = fmaf(dzs, fmaf(dzs, t[7], 2.0f * t[6]), t[5]);
+    m.WT = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
+    const float rx = fmaf(d0, tx, m.X) - p.btx * d0;
+    const float ry = fmaf(d0, ty, m.Y) - p.bty * d0;
+    m.chi2 = m.WT * fmaf(rx, rx, ry * ry);
+    return m;
+}
+
 // Stage boundaries for the per-stage cycle counters of the debug variant.
 struct Stamps {
     unsigned long long t[9];

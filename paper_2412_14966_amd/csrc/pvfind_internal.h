@@ -31,6 +31,10 @@ struct KParams {
     float chi2_max, inv_chi2_max, conv_dchi2, conv_dz, max_rho2_pp, cond_fp64, sing_ratio;
     int max_tracks, max_vertices;
     float bx, by, btx, bty;
+    // multi-vertex variant (Eq. 18)
+    int mv;
+    float e_max_mv;             // exp(-chi2_max_mv / 2)
+    float chi2_window_mv, conv_dz_mv, dup_ratio, w_count_mv;
 };
 
 // Device workspace of one stream: work-queue counters, the list of events

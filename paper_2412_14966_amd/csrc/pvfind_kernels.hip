@@ -55,7 +55,7 @@ constexpr int kSmallVertices = 64;  // clusters a small team holds
 // are neighbours in LDS and every window, run and cluster maps to LDS by one
 // offset.  Events that touch more than kPages words or give more than
 // kSmallVertices clusters go to the large-team launch.
-template <int W, int CAP, bool BIG>
+template <int W, int CAP, bool BIG, bool MV>
 struct __align__(16) Smem {
     static constexpr int V = BIG ? kMaxVertices : kSmallVertices;
     union {
@@ -67,11 +67,14 @@ struct __align__(16) Smem {
             int tw[CAP];     // its window jl | jh << 16, 0 for none
         } pp;
         struct {
+            // one slot per (vertex, track) pair of the fit, by vertex
             float X[CAP];    // track x at the seed z, relative to the seed
             float Y[CAP];
             float TX[CAP];
             float TY[CAP];
             float WT[CAP];   // 1 / V_x at the seed (Eq. 2), 0 for unusable tracks
+            float OTH[MV ? CAP : 1];      // multi-vertex: the other candidates' terms of Eq. 18
+            unsigned BEST[MV ? CAP : 1];  // multi-vertex, per track: best weight | vertex
             short IDX[CAP];  // track index within the event
         } f;
     } u;
@@ -93,13 +96,15 @@ struct __align__(16) Smem {
         };
     };
     int vout[V];
+    int ntk[MV ? V : 1];     // multi-vertex: tracks of final weight >= w_count_mv
+    float czz[MV ? V : 1];   // multi-vertex: C_zz for the duplicate test
     unsigned long long occ;
-    int ev, status, n_cl, n_live, done, n_keep, defer;
+    int ev, status, n_cl, n_live, done, n_keep, defer, n_slots;
 };
 
 // the histogram as the team holds it: h[j + off] is bin j
-template <int W, int CAP, bool BIG>
-__device__ __forceinline__ int *hist_lds(Smem<W, CAP, BIG> &S)
+template <int W, int CAP, bool BIG, bool MV>
+__device__ __forceinline__ int *hist_lds(Smem<W, CAP, BIG, MV> &S)
 {
     if constexpr (BIG)
         return S.u.hist;
@@ -114,8 +119,8 @@ __device__ __forceinline__ int page_off(unsigned long long occ, int w)
     return 64 * (__popcll(occ & ((1ull << w) - 1ull)) - w);
 }
 
-template <int W, int CAP, bool BIG>
-__device__ __forceinline__ int bin_value(Smem<W, CAP, BIG> &S, unsigned long long occ, int j)
+template <int W, int CAP, bool BIG, bool MV>
+__device__ __forceinline__ int bin_value(Smem<W, CAP, BIG, MV> &S, unsigned long long occ, int j)
 {
     if constexpr (BIG) {
         return S.u.hist[j];
@@ -128,12 +133,12 @@ __device__ __forceinline__ int bin_value(Smem<W, CAP, BIG> &S, unsigned long lon
 // Whole peak search, run by wavefront 0.  Proto-cluster runs come from
 // ballots of (bin > proto_thr) over the touched 64-bin words; they are queued
 // and walked 32-64 at a time, one lane per proto-cluster.
-template <int W, int CAP, bool BIG>
-__device__ __forceinline__ void peak_search(Smem<W, CAP, BIG> &S, const KParams &p)
+template <int W, int CAP, bool BIG, bool MV>
+__device__ __forceinline__ void peak_search(Smem<W, CAP, BIG, MV> &S, const KParams &p)
 {
     const int lane = threadIdx.x & 63;
     int *h = hist_lds(S);
-    const int cap = BIG ? p.max_vertices : min(p.max_vertices, Smem<W, CAP, BIG>::V);
+    const int cap = BIG ? p.max_vertices : min(p.max_vertices, Smem<W, CAP, BIG, MV>::V);
     int n_found = 0, npend = 0, open_s = -1, open_off = 0, prev_w = -2, pgi = 0;
     const unsigned long long occ0 = S.occ;
     unsigned long long occ = occ0;
@@ -245,8 +250,8 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP, BIG> &S, const KParams 
 
 // L = 1 << lg lanes per vertex, wavefront-uniform (scalar): one copy of the
 // code serves every group size.
-template <int W, int CAP, bool BIG>
-__device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams &p, int nl, int L, int lg)
+template <int W, int CAP, bool BIG, bool MV>
+__device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KParams &p, int nl, int L, int lg)
 {
     constexpr int NT = 64 * W;
     const int G = NT >> lg;
@@ -257,6 +262,7 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
         const bool has = k < nl;
         const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
         float rX[kRegTracks], rY[kRegTracks], rTX[kRegTracks], rTY[kRegTracks], rW[kRegTracks];
+        float rO[MV ? kRegTracks : 1];
 #pragma unroll
         for (int u = 0; u < kRegTracks; ++u) {
             const int t = gl + u * L;
@@ -267,8 +273,12 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
                 rTX[u] = S.u.f.TX[sl];
                 rTY[u] = S.u.f.TY[sl];
                 rW[u] = S.u.f.WT[sl];
+                if constexpr (MV)
+                    rO[u] = S.u.f.OTH[sl];
             } else {
                 rX[u] = rY[u] = rTX[u] = rTY[u] = rW[u] = 0.0f;
+                if constexpr (MV)
+                    rO[u] = 0.0f;
             }
         }
         // start at the seed: on the beamline, delta dz above the bin centre
@@ -283,13 +293,22 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
             if (active) {
 #pragma unroll
                 for (int u = 0; u < kRegTracks; ++u)
-                    if (rW[u] > 0.0f)
-                        accumulate(a, rX[u], rY[u], rTX[u], rTY[u], rW[u], dx, dy, dz, p);
+                    if (rW[u] > 0.0f) {
+                        if constexpr (MV)
+                            accumulate_mv(a, rX[u], rY[u], rTX[u], rTY[u], rW[u], rO[u], dx, dy, dz, p);
+                        else
+                            accumulate(a, rX[u], rY[u], rTX[u], rTY[u], rW[u], dx, dy, dz, p);
+                    }
                 for (int t = gl + kRegTracks * L; t < ck; t += L) {
                     const int sl = beg + t;
                     const float wt = S.u.f.WT[sl];
-                    if (wt > 0.0f)
-                        accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
+                    if (wt > 0.0f) {
+                        if constexpr (MV)
+                            accumulate_mv(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, S.u.f.OTH[sl],
+                                          dx, dy, dz, p);
+                        else
+                            accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
+                    }
                 }
             }
             float r[7] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz};
@@ -317,7 +336,8 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
                     lc = sy;
                     ld = szz;
                     nit = it;
-                    if (fabsf(dchi2) < p.conv_dchi2 && fabsf(ddz) < p.conv_dz) {
+                    // x86 criterion, or the GPU variant's |dz| alone (Sec. 3.5)
+                    if (MV ? (fabsf(ddz) < p.conv_dz_mv) : (fabsf(dchi2) < p.conv_dchi2 && fabsf(ddz) < p.conv_dz)) {
                         conv = true;
                         active = false;
                     }
@@ -337,16 +357,38 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG> &S, const KParams
     }
 }
 
-// Final Tukey weights at the fitted position, per-track outputs, chi2 and
-// ndof (2 sum w - 3), covariance (Eq. 14) and the vertex record.
-template <int W, int CAP, bool BIG>
-__device__ __forceinline__ void final_pass(Smem<W, CAP, BIG> &S, const KArgs &A, int e, int a, int nl, int L, int lg)
+// Final weights at the fitted position (Tukey, or Eq. 18 for the multi-vertex
+// variant), per-track outputs, chi2 and ndof (2 sum w - 3), covariance
+// (Eq. 14) and the vertex record.  Multi-vertex: a track may sit in several
+// candidates' lists; each written vertex offers it (weight, vertex) through an
+// LDS maximum over keys (top 24 bits of the weight, then the lower vertex
+// index), and the winning slot writes the track's outputs.
+template <int W, int CAP, bool BIG, bool MV>
+__device__ __forceinline__ void final_pass(Smem<W, CAP, BIG, MV> &S, const KArgs &A, int e, int a, int n, int nl,
+                                           int L, int lg)
 {
     constexpr int NT = 64 * W;
     const int G = NT >> lg;
     const KParams &p = A.p;
     const int tid = threadIdx.x;
     const int gid = tid >> lg, gl = tid & (L - 1);
+    auto weight_at = [&](int sl, float dx, float dy, float dz, float &chi2) __attribute__((always_inline)) -> float {
+        const float wt = S.u.f.WT[sl];
+        float w = 0.0f;
+        chi2 = 0.0f;
+        if (wt > 0.0f) {
+            const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
+            const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
+            chi2 = wt * fmaf(rx, rx, ry * ry);
+            if constexpr (MV) {
+                w = mv_weight(chi2, S.u.f.OTH[sl], p);
+            } else if (chi2 < p.chi2_max) {
+                const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
+                w = u * u;
+            }
+        }
+        return w;
+    };
     for (int k0 = 0; k0 < nl; k0 += G) {
         const int k = k0 + gid;
         const bool has = k < nl;
@@ -356,22 +398,18 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG> &S, const KArgs &A,
         float schi = 0.0f, sw = 0.0f;
         for (int t = gl; t < ck; t += L) {
             const int sl = beg + t;
-            const float wt = S.u.f.WT[sl];
-            float w = 0.0f, chi2 = 0.0f;
-            if (wt > 0.0f) {
-                const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
-                const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
-                chi2 = wt * fmaf(rx, rx, ry * ry);
-                if (chi2 < p.chi2_max) {
-                    const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
-                    w = u * u;
-                }
-            }
+            float chi2;
+            const float w = weight_at(sl, dx, dy, dz, chi2);
             schi = fmaf(w, chi2, schi);
             sw += w;
-            const int g = a + S.u.f.IDX[sl];
-            A.trk_vtx[g] = vo;
-            A.trk_w[g] = (vo >= 0) ? w : 0.0f;
+            if constexpr (MV) {
+                if (vo >= 0)
+                    atomicMax(&S.u.f.BEST[S.u.f.IDX[sl]], (__float_as_uint(w) & 0xFFFFFF00u) | (255u - (unsigned)vo));
+            } else {
+                const int g = a + S.u.f.IDX[sl];
+                A.trk_vtx[g] = vo;
+                A.trk_w[g] = (vo >= 0) ? w : 0.0f;
+            }
         }
         schi = group_sum_rt(schi, L);
         sw = group_sum_rt(sw, L);
@@ -403,7 +441,7 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG> &S, const KArgs &A,
             v.chi2 = schi;
             v.ndof = 2.0f * sw - 3.0f;
             v.z_seed = zr + S.cd0[cq];
-            v.n_tracks = S.cnt[k];
+            v.n_tracks = MV ? S.ntk[k] : S.cnt[k];
             v.bin_lo = S.clo[cq];
             v.bin_hi = S.chi[cq];
             v.peak_bin = S.cpk[cq];
@@ -413,13 +451,41 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG> &S, const KArgs &A,
             A.vout[(size_t)e * p.max_vertices + vo] = v;
         }
     }
+    if constexpr (MV) {
+        __syncthreads();
+        // tracks no written vertex took
+        for (int i = tid; i < n; i += NT)
+            if (S.u.f.BEST[i] == 0u) {
+                A.trk_vtx[a + i] = -1;
+                A.trk_w[a + i] = 0.0f;
+            }
+        // the winning slot of every other track
+        for (int k0 = 0; k0 < nl; k0 += G) {
+            const int k = k0 + gid;
+            const bool has = k < nl;
+            const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+            const int vo = has ? S.vout[k] : -1;
+            if (vo < 0)
+                continue;
+            const float dx = S.vf.dx[k], dy = S.vf.dy[k], dz = S.vf.dz[k];
+            for (int t = gl; t < ck; t += L) {
+                const int sl = beg + t;
+                const int i = S.u.f.IDX[sl];
+                if ((S.u.f.BEST[i] & 0xFFu) == 255u - (unsigned)vo) {
+                    float chi2;
+                    A.trk_vtx[a + i] = vo;
+                    A.trk_w[a + i] = weight_at(sl, dx, dy, dz, chi2);
+                }
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // one event
 // ---------------------------------------------------------------------------
-template <int W, int CAP, bool BIG, bool DEBUG>
-__device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs &A, int e, int n_events)
+template <int W, int CAP, bool BIG, bool MV, bool DEBUG>
+__device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KArgs &A, int e, int n_events)
 {
     constexpr int NT = 64 * W;
     const KParams &p = A.p;
@@ -628,177 +694,330 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs 
     }
     stamp<DEBUG>(ts, 3);
 
-    // association with iterative removal (Sec. 3.4)
-    if (wave == 0) {
-        for (int q = lane; q < S.n_cl; q += 64)
-            S.live[q] = (short)q;
-        if (lane == 0)
-            S.n_live = S.n_cl;
-    }
-    __syncthreads();
-    for (;;) {
-        const int nl = S.n_live;
+    int nl;
+    if constexpr (!MV) {
+        // association with iterative removal (Sec. 3.4)
         if (wave == 0) {
-            for (int k = lane; k < nl; k += 64) {
-                const int cq = S.live[k];
-                S.pb[k] = (k + 1 < nl) ? ((S.chi[cq] + S.clo[S.live[k + 1]]) >> 1) : p.nb - 1;
-                S.cnt[k] = 0;
-            }
+            for (int q = lane; q < S.n_cl; q += 64)
+                S.live[q] = (short)q;
+            if (lane == 0)
+                S.n_live = S.n_cl;
         }
         __syncthreads();
-        for (int i = tid; i < n; i += NT) {
-            const int t = S.tb[i];
-            int own = -1;
-            if (((t >> 13) & kTrAssoc) && nl > 0) {
-                own = lower_bound_bins(S.pb, nl, (t & 0x1FFF) - 1);
-                atomicAdd(&S.cnt[own], 1);
+        for (;;) {
+            const int nl = S.n_live;
+            if (wave == 0) {
+                for (int k = lane; k < nl; k += 64) {
+                    const int cq = S.live[k];
+                    S.pb[k] = (k + 1 < nl) ? ((S.chi[cq] + S.clo[S.live[k + 1]]) >> 1) : p.nb - 1;
+                    S.cnt[k] = 0;
+                }
             }
-            S.tb[i] = (t & 0xFFFF) | ((own + 1) << 16);
+            __syncthreads();
+            for (int i = tid; i < n; i += NT) {
+                const int t = S.tb[i];
+                int own = -1;
+                if (((t >> 13) & kTrAssoc) && nl > 0) {
+                    own = lower_bound_bins(S.pb, nl, (t & 0x1FFF) - 1);
+                    atomicAdd(&S.cnt[own], 1);
+                }
+                S.tb[i] = (t & 0xFFFF) | ((own + 1) << 16);
+            }
+            __syncthreads();
+            if (wave == 0) {
+                int key = INT_MAX;
+                for (int k = lane; k < nl; k += 64) {
+                    const int cq = S.live[k];
+                    const int need = (S.cpk[cq] < p.gas_bin) ? p.part_min_gas : p.part_min_pp;
+                    const int c = S.cnt[k];
+                    if (c < need)
+                        key = min(key, (c << 8) | k);
+                }
+                key = wave_min(key);
+                if (key == INT_MAX) {
+                    if (lane == 0)
+                        S.done = 1;
+                } else {
+                    const int kv = key & 0xFF;
+                    const int k0 = lane, k1 = lane + 64;
+                    short v0 = 0, v1 = 0;
+                    if (k0 < nl - 1)
+                        v0 = S.live[k0 + (k0 >= kv ? 1 : 0)];
+                    if (k1 < nl - 1)
+                        v1 = S.live[k1 + (k1 >= kv ? 1 : 0)];
+                    __builtin_amdgcn_wave_barrier();
+                    if (k0 < nl - 1)
+                        S.live[k0] = v0;
+                    if (k1 < nl - 1)
+                        S.live[k1] = v1;
+                    if (lane == 0)
+                        S.n_live = nl - 1;
+                }
+            }
+            __syncthreads();
+            if (S.done)
+                break;
         }
-        __syncthreads();
-        if (wave == 0) {
-            int key = INT_MAX;
-            for (int k = lane; k < nl; k += 64) {
-                const int cq = S.live[k];
-                const int need = (S.cpk[cq] < p.gas_bin) ? p.part_min_gas : p.part_min_pp;
-                const int c = S.cnt[k];
-                if (c < need)
-                    key = min(key, (c << 8) | k);
+        nl = S.n_live;
+        stamp<DEBUG>(ts, 4);
+
+        if (DEBUG && A.dbg_cl && wave == 0) {
+            for (int q = lane; q < S.n_cl; q += 64)
+                S.vout[q] = -1;
+            __builtin_amdgcn_wave_barrier();
+            for (int k = lane; k < nl; k += 64)
+                S.vout[S.live[k]] = k;
+            __builtin_amdgcn_wave_barrier();
+            for (int q = lane; q < S.n_cl; q += 64) {
+                const int k = S.vout[q];
+                pv_cluster c;
+                c.lo = S.clo[q];
+                c.hi = S.chi[q];
+                c.peak = S.cpk[q];
+                c.z_seed = bin_centre(S.cpk[q], p) + S.cd0[q];
+                c.kept = (k >= 0) ? 1 : 0;
+                c.n_assoc = (k >= 0) ? S.cnt[k] : 0;
+                c.own_lo = (k > 0) ? S.pb[k - 1] + 1 : (k == 0 ? 0 : -1);
+                c.own_hi = (k >= 0) ? S.pb[k] : -1;
+                A.dbg_cl[(size_t)e * p.max_vertices + q] = c;
             }
-            key = wave_min(key);
-            if (key == INT_MAX) {
-                if (lane == 0)
-                    S.done = 1;
-            } else {
-                const int kv = key & 0xFF;
-                const int k0 = lane, k1 = lane + 64;
-                short v0 = 0, v1 = 0;
-                if (k0 < nl - 1)
-                    v0 = S.live[k0 + (k0 >= kv ? 1 : 0)];
-                if (k1 < nl - 1)
-                    v1 = S.live[k1 + (k1 >= kv ? 1 : 0)];
+        }
+
+        // gather tracks by vertex (stable, by track index)
+        if (wave == 0) {
+            const int c0 = (lane < nl) ? S.cnt[lane] : 0;
+            const int c1 = (lane + 64 < nl) ? S.cnt[lane + 64] : 0;
+            const int i0 = wave_incl_scan(c0, lane);
+            const int t0 = __shfl(i0, 63);
+            const int i1 = wave_incl_scan(c1, lane);
+            if (lane < nl)
+                S.base[lane] = i0 - c0;
+            if (lane + 64 < nl)
+                S.base[lane + 64] = t0 + i1 - c1;
+        }
+        if (W > 1) {
+            for (int k = tid; k < W * Smem<W, CAP, BIG, MV>::V; k += NT)
+                (&S.wrun[0][0])[k] = 0;
+            __syncthreads();
+            for (int i = r0 + lane; i < r1; i += 64) {
+                const int own = (S.tb[i] >> 16) - 1;
+                if (own >= 0)
+                    atomicAdd(&S.wrun[wave][own], 1);
+            }
+            __syncthreads();
+            for (int k = tid; k < nl; k += NT) {
+                int run = S.base[k];
+                for (int w = 0; w < W; ++w) {
+                    const int t = S.wrun[w][k];
+                    S.wrun[w][k] = run;
+                    run += t;
+                }
+            }
+            __syncthreads();
+        } else {
+            __syncthreads();
+            for (int k = tid; k < nl; k += NT)
+                S.wrun[0][k] = S.base[k];
+            __syncthreads();
+        }
+        for (int c0 = r0; c0 < r1; c0 += 64) {
+            const int i = c0 + lane;
+            const bool valid = i < r1;
+            const int own = valid ? (S.tb[i] >> 16) - 1 : -1;
+            float t[8];
+    #pragma unroll
+            for (int q = 0; q < 8; ++q)
+                t[q] = gnext[q];
+            if (c0 + 64 + lane < r1)
+                load_track(A, a + c0 + 64 + lane, gnext);
+            unsigned long long rem = __ballot(own >= 0);
+            int slot = -1;
+            while (rem) {
+                const int leader = __ffsll((long long)rem) - 1;
+                const int ol = __shfl(own, leader);
+                const unsigned long long mm = __ballot(own == ol);
+                if (own == ol)
+                    slot = S.wrun[wave][ol] + __popcll(mm & lanemask_lt(lane));
                 __builtin_amdgcn_wave_barrier();
-                if (k0 < nl - 1)
-                    S.live[k0] = v0;
-                if (k1 < nl - 1)
-                    S.live[k1] = v1;
-                if (lane == 0)
-                    S.n_live = nl - 1;
+                if (lane == leader)
+                    S.wrun[wave][ol] += __popcll(mm);
+                __builtin_amdgcn_wave_barrier();
+                rem &= ~mm;
+            }
+            if (valid) {
+                const int g = a + i;
+                if (slot >= 0) {
+                    const float x = t[0], y = t[1], z = t[2], tx = t[3], ty = t[4];
+                    const float vxx = t[5], vxtx = t[6], vtxtx = t[7];
+                    // positions relative to the beamline point at the peak-bin centre
+                    const int cq = S.live[own];
+                    const float zr = bin_centre(S.cpk[cq], p);
+                    const float dzr = zr - z;
+                    S.u.f.X[slot] = fmaf(dzr, tx, x) - (p.bx + p.btx * zr);
+                    S.u.f.Y[slot] = fmaf(dzr, ty, y) - (p.by + p.bty * zr);
+                    S.u.f.TX[slot] = tx;
+                    S.u.f.TY[slot] = ty;
+                    // Eq. 2 at the seed: z_seed - z_trk = (z_i - z_trk) + delta dz
+                    const float dzs = dzr + S.cd0[cq];
+                    const float V = fmaf(dzs, fmaf(dzs, vtxtx, 2.0f * vxtx), vxx);
+                    S.u.f.WT[slot] = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
+                    S.u.f.IDX[slot] = (short)i;
+                } else {
+                    A.trk_vtx[g] = -1;
+                    A.trk_w[g] = 0.0f;
+                }
             }
         }
-        __syncthreads();
-        if (S.done)
-            break;
-    }
-    const int nl = S.n_live;
-    stamp<DEBUG>(ts, 4);
-
-    if (DEBUG && A.dbg_cl && wave == 0) {
-        for (int q = lane; q < S.n_cl; q += 64)
-            S.vout[q] = -1;
-        __builtin_amdgcn_wave_barrier();
-        for (int k = lane; k < nl; k += 64)
-            S.vout[S.live[k]] = k;
-        __builtin_amdgcn_wave_barrier();
-        for (int q = lane; q < S.n_cl; q += 64) {
-            const int k = S.vout[q];
-            pv_cluster c;
-            c.lo = S.clo[q];
-            c.hi = S.chi[q];
-            c.peak = S.cpk[q];
-            c.z_seed = bin_centre(S.cpk[q], p) + S.cd0[q];
-            c.kept = (k >= 0) ? 1 : 0;
-            c.n_assoc = (k >= 0) ? S.cnt[k] : 0;
-            c.own_lo = (k > 0) ? S.pb[k - 1] + 1 : (k == 0 ? 0 : -1);
-            c.own_hi = (k >= 0) ? S.pb[k] : -1;
-            A.dbg_cl[(size_t)e * p.max_vertices + q] = c;
+    } else {
+        // Multi-vertex (Sec. 3.5, Sec. 5): every cluster is a candidate and
+        // fits the tracks passing its pre-cut; one slot per (candidate, track)
+        // pair, by candidate and, within one, by track index (each wavefront
+        // takes its contiguous range of tracks, ranks within a chunk by
+        // ballot), so the sums are reproducible.
+        if (wave == 0) {
+            for (int q = lane; q < S.n_cl; q += 64)
+                S.live[q] = (short)q;
+            if (lane == 0)
+                S.n_live = S.n_cl;
         }
-    }
-
-    // gather tracks by vertex (stable, by track index)
-    if (wave == 0) {
-        const int c0 = (lane < nl) ? S.cnt[lane] : 0;
-        const int c1 = (lane + 64 < nl) ? S.cnt[lane + 64] : 0;
-        const int i0 = wave_incl_scan(c0, lane);
-        const int t0 = __shfl(i0, 63);
-        const int i1 = wave_incl_scan(c1, lane);
-        if (lane < nl)
-            S.base[lane] = i0 - c0;
-        if (lane + 64 < nl)
-            S.base[lane + 64] = t0 + i1 - c1;
-    }
-    if (W > 1) {
-        for (int k = tid; k < W * Smem<W, CAP, BIG>::V; k += NT)
+        for (int k = tid; k < W * Smem<W, CAP, BIG, MV>::V; k += NT)
             (&S.wrun[0][0])[k] = 0;
         __syncthreads();
-        for (int i = r0 + lane; i < r1; i += 64) {
-            const int own = (S.tb[i] >> 16) - 1;
-            if (own >= 0)
-                atomicAdd(&S.wrun[wave][own], 1);
-        }
-        __syncthreads();
-        for (int k = tid; k < nl; k += NT) {
-            int run = S.base[k];
-            for (int w = 0; w < W; ++w) {
-                const int t = S.wrun[w][k];
-                S.wrun[w][k] = run;
-                run += t;
-            }
-        }
-        __syncthreads();
-    } else {
-        __syncthreads();
-        for (int k = tid; k < nl; k += NT)
-            S.wrun[0][k] = S.base[k];
-        __syncthreads();
-    }
-    for (int c0 = r0; c0 < r1; c0 += 64) {
-        const int i = c0 + lane;
-        const bool valid = i < r1;
-        const int own = valid ? (S.tb[i] >> 16) - 1 : -1;
-        float t[8];
+        nl = S.n_live;
+        stamp<DEBUG>(ts, 4);
+        auto chunk_tracks = [&](int c0, float t[8]) __attribute__((always_inline)) {
+            if (c0 == r0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            t[q] = gnext[q];
-        if (c0 + 64 + lane < r1)
-            load_track(A, a + c0 + 64 + lane, gnext);
-        unsigned long long rem = __ballot(own >= 0);
-        int slot = -1;
-        while (rem) {
-            const int leader = __ffsll((long long)rem) - 1;
-            const int ol = __shfl(own, leader);
-            const unsigned long long mm = __ballot(own == ol);
-            if (own == ol)
-                slot = S.wrun[wave][ol] + __popcll(mm & lanemask_lt(lane));
-            __builtin_amdgcn_wave_barrier();
-            if (lane == leader)
-                S.wrun[wave][ol] += __popcll(mm);
-            __builtin_amdgcn_wave_barrier();
-            rem &= ~mm;
-        }
-        if (valid) {
-            const int g = a + i;
-            if (slot >= 0) {
-                const float x = t[0], y = t[1], z = t[2], tx = t[3], ty = t[4];
-                const float vxx = t[5], vxtx = t[6], vtxtx = t[7];
-                // positions relative to the beamline point at the peak-bin centre
-                const int cq = S.live[own];
-                const float zr = bin_centre(S.cpk[cq], p);
-                const float dzr = zr - z;
-                S.u.f.X[slot] = fmaf(dzr, tx, x) - (p.bx + p.btx * zr);
-                S.u.f.Y[slot] = fmaf(dzr, ty, y) - (p.by + p.bty * zr);
-                S.u.f.TX[slot] = tx;
-                S.u.f.TY[slot] = ty;
-                // Eq. 2 at the seed: z_seed - z_trk = (z_i - z_trk) + delta dz
-                const float dzs = dzr + S.cd0[cq];
-                const float V = fmaf(dzs, fmaf(dzs, vtxtx, 2.0f * vxtx), vxx);
-                S.u.f.WT[slot] = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
-                S.u.f.IDX[slot] = (short)i;
-            } else {
-                A.trk_vtx[g] = -1;
-                A.trk_w[g] = 0.0f;
+                for (int q = 0; q < 8; ++q)
+                    t[q] = gnext[q];
+            } else if (c0 + lane < r1) {
+                load_track(A, a + c0 + lane, t);
+            }
+        };
+        // pass 1: per wavefront and candidate, the tracks passing the pre-cut
+        for (int c0 = r0; c0 < r1; c0 += 64) {
+            const int i = c0 + lane;
+            float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            chunk_tracks(c0, t);
+            const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
+            for (int k = 0; k < nl; ++k) {
+                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
+                const unsigned long long mm = __ballot(assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv);
+                if (lane == 0)
+                    S.wrun[wave][k] += __popcll(mm);
             }
         }
+        __syncthreads();
+        // list lengths, starts and each wavefront's first slot per candidate
+        if (wave == 0) {
+            int run = 0;
+            for (int k0 = 0; k0 < nl; k0 += 64) {
+                const int k = k0 + lane;
+                int c = 0;
+                if (k < nl)
+                    for (int w = 0; w < W; ++w)
+                        c += S.wrun[w][k];
+                const int incl = wave_incl_scan(c, lane);
+                if (k < nl) {
+                    S.cnt[k] = c;
+                    S.base[k] = run + incl - c;
+                    int r = run + incl - c;
+                    for (int w = 0; w < W; ++w) {
+                        const int tw = S.wrun[w][k];
+                        S.wrun[w][k] = r;
+                        r += tw;
+                    }
+                }
+                run += __shfl(incl, 63);
+            }
+            if (lane == 0) {
+                S.n_slots = run;
+                // the lists share the event's track capacity (else the event is
+                // flagged), and must fit the team's slots (else deferred)
+                if (run > p.max_tracks)
+                    S.status |= PV_EV_TOO_MANY_TRACKS;
+                else if (!BIG && run > CAP)
+                    S.defer = 1;
+            }
+        }
+        __syncthreads();
+        if (!BIG && S.defer) {
+            defer();
+            return;
+        }
+        if (S.n_slots > p.max_tracks) {
+            for (int i = tid; i < n; i += NT) {
+                A.trk_vtx[a + i] = -1;
+                A.trk_w[a + i] = 0.0f;
+            }
+            if (tid == 0) {
+                A.nv_out[e] = 0;
+                A.status_out[e] = S.status;
+                if (DEBUG && A.dbg_ncl)
+                    A.dbg_ncl[e] = S.n_cl;
+            }
+            if (DEBUG && A.dbg_cl && wave == 0)
+                for (int q = lane; q < S.n_cl; q += 64) {
+                    pv_cluster c;
+                    c.lo = S.clo[q];
+                    c.hi = S.chi[q];
+                    c.peak = S.cpk[q];
+                    c.z_seed = bin_centre(S.cpk[q], p) + S.cd0[q];
+                    c.kept = 1;
+                    c.n_assoc = S.cnt[q];
+                    c.own_lo = c.own_hi = -1;
+                    A.dbg_cl[(size_t)e * p.max_vertices + q] = c;
+                }
+            __syncthreads();
+            return;
+        }
+        // pass 2: write the slots; the other candidates' terms of Eq. 18 are
+        // the track's sum over its pre-cut passes minus this candidate's
+        for (int c0 = r0; c0 < r1; c0 += 64) {
+            const int i = c0 + lane;
+            float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            chunk_tracks(c0, t);
+            const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
+            float esum = 0.0f;
+            for (int k = 0; k < nl; ++k) {
+                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
+                if (assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv)
+                    esum += __expf(-0.5f * m.chi2);
+            }
+            if (i < r1)
+                S.u.f.BEST[i] = 0u;
+            for (int k = 0; k < nl; ++k) {
+                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
+                const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
+                const unsigned long long mm = __ballot(pass);
+                if (pass) {
+                    const int slot = S.wrun[wave][k] + __popcll(mm & lanemask_lt(lane));
+                    S.u.f.X[slot] = m.X;
+                    S.u.f.Y[slot] = m.Y;
+                    S.u.f.TX[slot] = t[3];
+                    S.u.f.TY[slot] = t[4];
+                    S.u.f.WT[slot] = m.WT;
+                    S.u.f.OTH[slot] = fmaxf(esum - __expf(-0.5f * m.chi2), 0.0f);
+                    S.u.f.IDX[slot] = (short)i;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0)
+                    S.wrun[wave][k] += __popcll(mm);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (DEBUG && A.dbg_cl && wave == 0)
+            for (int q = lane; q < S.n_cl; q += 64) {
+                pv_cluster c;
+                c.lo = S.clo[q];
+                c.hi = S.chi[q];
+                c.peak = S.cpk[q];
+                c.z_seed = bin_centre(S.cpk[q], p) + S.cd0[q];
+                c.kept = 1;
+                c.n_assoc = S.cnt[q];
+                c.own_lo = c.own_hi = -1;
+                A.dbg_cl[(size_t)e * p.max_vertices + q] = c;
+            }
     }
     __syncthreads();
     stamp<DEBUG>(ts, 5);
@@ -817,43 +1036,166 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs 
     }
     lg = __builtin_amdgcn_readfirstlane(lg);   // the same on every lane: keep it scalar
     const int L = 1 << lg;
-    fit_vertices<W, CAP, BIG>(S, p, nl, L, lg);
+    fit_vertices<W, CAP, BIG, MV>(S, p, nl, L, lg);
     __syncthreads();
     stamp<DEBUG>(ts, 6);
 
-    // final selection (Table 2, end of Sec. 3.5)
-    if (wave == 0) {
-        int kept = 0;
-        for (int k0 = 0; k0 < nl; k0 += 64) {
-            const int k = k0 + lane;
-            bool keep = false;
-            if (k < nl) {
-                const int cq = S.live[k];
-                const bool gas = S.cpk[cq] < p.gas_bin;
-                keep = !(S.vf.info[k] & kInfoFailed) && S.cnt[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
-                if (keep && !gas) {
-                    const float zr = bin_centre(S.cpk[cq], p);
-                    const float zv = zr + S.vf.dz[k];
-                    const float xv = (p.bx + p.btx * zr) + S.vf.dx[k];
-                    const float yv = (p.by + p.bty * zr) + S.vf.dy[k];
-                    const float rx = xv - (p.bx + p.btx * zv);
-                    const float ry = yv - (p.by + p.bty * zv);
-                    keep = fmaf(rx, rx, ry * ry) <= p.max_rho2_pp;
+    if constexpr (!MV) {
+        // final selection (Table 2, end of Sec. 3.5)
+        if (wave == 0) {
+            int kept = 0;
+            for (int k0 = 0; k0 < nl; k0 += 64) {
+                const int k = k0 + lane;
+                bool keep = false;
+                if (k < nl) {
+                    const int cq = S.live[k];
+                    const bool gas = S.cpk[cq] < p.gas_bin;
+                    keep = !(S.vf.info[k] & kInfoFailed) && S.cnt[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
+                    if (keep && !gas) {
+                        const float zr = bin_centre(S.cpk[cq], p);
+                        const float zv = zr + S.vf.dz[k];
+                        const float xv = (p.bx + p.btx * zr) + S.vf.dx[k];
+                        const float yv = (p.by + p.bty * zr) + S.vf.dy[k];
+                        const float rx = xv - (p.bx + p.btx * zv);
+                        const float ry = yv - (p.by + p.bty * zv);
+                        keep = fmaf(rx, rx, ry * ry) <= p.max_rho2_pp;
+                    }
+                }
+                const unsigned long long km = __ballot(keep);
+                if (k < nl)
+                    S.vout[k] = keep ? kept + __popcll(km & lanemask_lt(lane)) : -1;
+                kept += __popcll(km);
+            }
+            if (lane == 0)
+                S.n_keep = kept;
+        }
+    } else {
+        // Multi-vertex: track counts (final weight >= w_count_mv) and C_zz of
+        // every candidate, then duplicates and the selection of Table 2
+        {
+            const int G = NT >> lg;
+            const int gid = tid >> lg, gl = tid & (L - 1);
+            for (int k0 = 0; k0 < nl; k0 += G) {
+                const int k = k0 + gid;
+                const bool has = k < nl;
+                const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
+                const float dx = has ? S.vf.dx[k] : 0.0f, dy = has ? S.vf.dy[k] : 0.0f, dz = has ? S.vf.dz[k] : 0.0f;
+                float c = 0.0f;
+                for (int t = gl; t < ck; t += L) {
+                    const int sl = beg + t;
+                    const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
+                    const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
+                    const float chi2 = S.u.f.WT[sl] * fmaf(rx, rx, ry * ry);
+                    c += (mv_weight(chi2, S.u.f.OTH[sl], p) >= p.w_count_mv) ? 1.0f : 0.0f;
+                }
+                c = group_sum_rt(c, L);
+                if (has && gl == 0) {
+                    S.ntk[k] = (int)c;
+                    const float la = S.vf.a[k], lb = S.vf.b[k], lc = S.vf.c[k], ld = S.vf.d[k];
+                    float cf[6];
+                    const float det = inverse_a<float>(la, lb, lc, ld, cf);
+                    const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
+                    const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
+                                                 fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
+                                           fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
+                    if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
+                        double cd[6];
+                        inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
+                        cf[5] = (float)cd[5];
+                    }
+                    S.czz[k] = cf[5];
                 }
             }
-            const unsigned long long km = __ballot(keep);
-            if (k < nl)
-                S.vout[k] = keep ? kept + __popcll(km & lanemask_lt(lane)) : -1;
-            kept += __popcll(km);
         }
-        if (lane == 0)
-            S.n_keep = kept;
+        __syncthreads();
+        if (wave == 0) {
+            constexpr int KPL = (Smem<W, CAP, BIG, MV>::V + 63) / 64;   // candidates per lane
+            bool ok[KPL], kept[KPL];
+            int rank[KPL];
+            float zk[KPL], cz[KPL];
+            int n_ok = 0;
+#pragma unroll
+            for (int u = 0; u < KPL; ++u) {
+                const int k = lane + 64 * u;
+                ok[u] = k < nl && !(S.vf.info[k] & kInfoFailed);
+                kept[u] = false;
+                zk[u] = ok[u] ? bin_centre(S.cpk[S.live[k]], p) + S.vf.dz[k] : 0.0f;
+                cz[u] = ok[u] ? S.czz[k] : 0.0f;
+                rank[u] = 0;
+                if (ok[u]) {
+                    const int nk = S.ntk[k];
+                    for (int q = 0; q < nl; ++q) {
+                        if (q == k || (S.vf.info[q] & kInfoFailed))
+                            continue;
+                        const int nq = S.ntk[q];
+                        rank[u] += (nq > nk || (nq == nk && q < k)) ? 1 : 0;
+                    }
+                }
+                n_ok += __popcll(__ballot(ok[u]));
+            }
+            // by rank: kept unless a duplicate of one kept before it
+            for (int r = 0; r < n_ok; ++r) {
+                int src = 0, su = 0;
+#pragma unroll
+                for (int u = 0; u < KPL; ++u) {
+                    const unsigned long long hm = __ballot(ok[u] && rank[u] == r);
+                    if (hm) {
+                        src = __ffsll((long long)hm) - 1;
+                        su = u;
+                    }
+                }
+                float zc = 0.0f, cc = 0.0f;
+#pragma unroll
+                for (int u = 0; u < KPL; ++u)
+                    if (u == su) {
+                        zc = __shfl(zk[u], src);
+                        cc = __shfl(cz[u], src);
+                    }
+                bool dup = false;
+#pragma unroll
+                for (int u = 0; u < KPL; ++u) {
+                    const float d = zc - zk[u];
+                    dup = dup || (kept[u] && d * d < p.dup_ratio * (cc + cz[u]));
+                }
+                const bool any = __ballot(dup) != 0ull;
+#pragma unroll
+                for (int u = 0; u < KPL; ++u)
+                    if (u == su && lane == src)
+                        kept[u] = !any;
+            }
+            int kept_n = 0;
+#pragma unroll
+            for (int u = 0; u < KPL; ++u) {
+                const int k = lane + 64 * u;
+                bool keep = false;
+                if (kept[u]) {
+                    const int cq = S.live[k];
+                    const bool gas = S.cpk[cq] < p.gas_bin;
+                    keep = S.ntk[k] >= (gas ? p.pv_min_gas : p.pv_min_pp);
+                    if (keep && !gas) {
+                        const float zr = bin_centre(S.cpk[cq], p);
+                        const float zv = zr + S.vf.dz[k];
+                        const float xv = (p.bx + p.btx * zr) + S.vf.dx[k];
+                        const float yv = (p.by + p.bty * zr) + S.vf.dy[k];
+                        const float rx = xv - (p.bx + p.btx * zv);
+                        const float ry = yv - (p.by + p.bty * zv);
+                        keep = fmaf(rx, rx, ry * ry) <= p.max_rho2_pp;
+                    }
+                }
+                const unsigned long long km = __ballot(keep);
+                if (k < nl)
+                    S.vout[k] = keep ? kept_n + __popcll(km & lanemask_lt(lane)) : -1;
+                kept_n += __popcll(km);
+            }
+            if (lane == 0)
+                S.n_keep = kept_n;
+        }
     }
     __syncthreads();
     stamp<DEBUG>(ts, 7);
 
     // final weights, vertex records
-    final_pass<W, CAP, BIG>(S, A, e, a, nl, L, lg);
+    final_pass<W, CAP, BIG, MV>(S, A, e, a, n, nl, L, lg);
     if (tid == 0) {
         A.nv_out[e] = S.n_keep;
         A.status_out[e] = S.status;
@@ -867,76 +1209,60 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG> &S, const KArgs 
             A.dbg_cycles[(size_t)e * 8 + k] = (uint32_t)(ts.t[k + 1] - ts.t[k]);
 }
 
-// mode 0: one workgroup per event (grid = n_events); mode 1: persistent grid
-// with a device work queue.  BIG kernels always take the deferred-event queue.
-template <int W, int CAP, bool BIG, bool DEBUG>
-__global__ __launch_bounds__(64 * W) void pv_find_kernel(KArgs A, int mode)
+// Large events: a persistent grid, one four-wavefront team per CU, drains the
+// list of events the small teams deferred.
+template <bool MV, bool DEBUG>
+__global__ __launch_bounds__(64 * kBigWaves) void pv_find_large(KArgs A)
 {
-    __shared__ Smem<W, CAP, BIG> S;
+    __shared__ Smem<kBigWaves, kBigCapacity, true, MV> S;
     const int tid = threadIdx.x;
     const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
-    // Nothing deferred: the large-team counters are all zero and stay so; leave
-    // without touching them (n_big is not written while this grid runs, so
-    // every workgroup sees the same value).
-    if (BIG && __hip_atomic_load(&A.wq->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+    // Nothing deferred: the counters are all zero and stay so; leave without
+    // touching them (n_big is not written while this grid runs, so every
+    // workgroup sees the same value).
+    if (__hip_atomic_load(&A.wq->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
         return;
-    bool first = true;
     for (;;) {
         if (tid == 0) {
             int e = -1;
-            if (BIG) {
-                const unsigned int k = atomicAdd(&A.wq->next_big, 1u);
-                const unsigned int nbig = atomicAdd(&A.wq->n_big, 0u);
-                if (k < nbig)
-                    e = A.wq->big[k];
-            } else if (mode == 1) {
-                const unsigned int k = atomicAdd(&A.wq->next, 1u);
-                if (k < (unsigned int)n_events)
-                    e = A.order ? A.order[k] : (int)k;
-            } else if (first && (int)blockIdx.x < n_events) {
-                e = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
-            }
+            const unsigned int k = atomicAdd(&A.wq->next_big, 1u);
+            const unsigned int nbig = atomicAdd(&A.wq->n_big, 0u);
+            if (k < nbig)
+                e = A.wq->big[k];
             S.ev = e;
         }
-        first = false;
         __syncthreads();
         const int e = S.ev;
         __syncthreads();
         if (e < 0)
             break;
-        process_event<W, CAP, BIG, DEBUG>(S, A, e, n_events);
+        process_event<kBigWaves, kBigCapacity, true, MV, DEBUG>(S, A, e, n_events);
     }
-    if (tid == 0 && (BIG || mode == 1)) {
+    if (tid == 0) {
         __threadfence();
-        unsigned int *done = BIG ? &A.wq->done_big : &A.wq->done;
-        const unsigned int prev = atomicAdd(done, 1u);
+        const unsigned int prev = atomicAdd(&A.wq->done_big, 1u);
         if (prev == gridDim.x - 1) {
-            if (BIG) {
-                atomicExch(&A.wq->next_big, 0u);
-                atomicExch(&A.wq->n_big, 0u);
-                atomicExch(&A.wq->done_big, 0u);
-            } else {
-                atomicExch(&A.wq->next, 0u);
-                atomicExch(&A.wq->done, 0u);
-            }
+            atomicExch(&A.wq->next_big, 0u);
+            atomicExch(&A.wq->n_big, 0u);
+            atomicExch(&A.wq->done_big, 0u);
             __threadfence();
         }
     }
 }
 
 // One small team per event, hardware-scheduled (grid = events, or the batch
-// capacity when the count is read from device memory).  Without the
-// persistent loop no value has to live from one event to the next, which
-// keeps the register footprint far below the persistent kernel's.
-template <int W, int CAP, bool DEBUG>
+// capacity when the count is read from device memory).  Without a persistent
+// loop no value has to live from one event to the next, which keeps the
+// register footprint low.
+template <int W, int CAP, bool MV, bool DEBUG>
 __global__ __launch_bounds__(64 * W) void pv_find_single(KArgs A)
 {
-    __shared__ Smem<W, CAP, false> S;
+    __shared__ Smem<W, CAP, false, MV> S;
     const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
     if ((int)blockIdx.x >= n_events)
         return;
     const int e = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
-    process_event<W, CAP, false, DEBUG>(S, A, e, n_events);
+    process_event<W, CAP, false, MV, DEBUG>(S, A, e, n_events);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,36 +1333,28 @@ static int device_cus()
     return cached_cus;
 }
 
-template <int W, int CAP, bool BIG, bool DEBUG>
-static hipError_t launch_one(const KArgs &A, int mode, int teams_per_cu, hipStream_t st)
+template <int W, int CAP, bool MV, bool DEBUG>
+static hipError_t launch_small(const KArgs &A, hipStream_t st)
 {
-    if (!BIG && mode == 0) {
-        if (A.n_events < 1)
-            return hipSuccess;
-        hipLaunchKernelGGL((pv_find_single<W, CAP, DEBUG>), dim3(A.n_events), dim3(64 * W), 0, st, A);
-        return hipGetLastError();
-    }
-    auto *fn = pv_find_kernel<W, CAP, BIG, DEBUG>;
-    int grid;
-    if (mode == 1 || BIG) {
-        int occ = 0;
-        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * W, 0);
-        if (err != hipSuccess)
-            return err;
-        if (occ < 1)
-            occ = 1;
-        if (teams_per_cu > 0 && teams_per_cu < occ)
-            occ = teams_per_cu;
-        const int cus = device_cus();
-        grid = occ * (cus > 0 ? cus : 256);
-        if (!BIG && grid > A.n_events)
-            grid = A.n_events;
-        if (grid < 1)
-            grid = 1;
-    } else {
-        grid = A.n_events;
-    }
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * W), 0, st, A, BIG ? 1 : mode);
+    if (A.n_events < 1)
+        return hipSuccess;
+    hipLaunchKernelGGL((pv_find_single<W, CAP, MV, DEBUG>), dim3(A.n_events), dim3(64 * W), 0, st, A);
+    return hipGetLastError();
+}
+
+template <bool MV, bool DEBUG>
+static hipError_t launch_large(const KArgs &A, hipStream_t st)
+{
+    auto *fn = pv_find_large<MV, DEBUG>;
+    int occ = 0;
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * kBigWaves, 0);
+    if (err != hipSuccess)
+        return err;
+    if (occ < 1)
+        occ = 1;
+    const int cus = device_cus();
+    const int grid = occ * (cus > 0 ? cus : 256);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * kBigWaves), 0, st, A);
     return hipGetLastError();
 }
 
@@ -1045,14 +1363,13 @@ static hipError_t record(void *ev, hipStream_t st)
     return ev ? hipEventRecord(reinterpret_cast<hipEvent_t>(ev), st) : hipSuccess;
 }
 
-template <int W, int CAP, bool DEBUG>
-static hipError_t launch_pair(const KArgs &args, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
+template <int W, int CAP, bool MV, bool DEBUG>
+static hipError_t launch_pair(const KArgs &args, hipStream_t st, LaunchEvents *ev)
 {
     KArgs A = args;
     if (!A.n_events_dev && A.n_events < 2)
         A.order = nullptr;   // nothing to order
     hipError_t err = hipSuccess;
-    const int mode = (s.persistent == 1 || s.persistent == 3) ? 1 : 0;
     if (A.order) {
         hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
                            A.order);
@@ -1062,39 +1379,38 @@ static hipError_t launch_pair(const KArgs &args, const pv_schedule &s, hipStream
     if (err == hipSuccess)
         err = record(ev ? ev->main_begin : nullptr, st);
     if (err == hipSuccess)
-        err = launch_one<W, CAP, false, DEBUG>(A, mode, s.teams_per_cu, st);
+        err = launch_small<W, CAP, MV, DEBUG>(A, st);
     if (err == hipSuccess)
         err = record(ev ? ev->main_end : nullptr, st);
     if (err != hipSuccess)
         return err;
     // events with more tracks than CAP, more touched histogram words than the
-    // pages or more clusters than the vertex slots of a small team were
-    // deferred to the large-team launch (which returns at once if none was)
-    {
-        if (ev)
-            ev->large = true;
-        err = record(ev ? ev->large_begin : nullptr, st);
-        if (err == hipSuccess)
-            err = launch_one<kBigWaves, kBigCapacity, true, DEBUG>(A, 1, 0, st);
-        if (err == hipSuccess)
-            err = record(ev ? ev->large_end : nullptr, st);
-    }
+    // pages, more clusters than the vertex slots or (multi-vertex) longer
+    // candidate track lists than a small team holds were deferred to the
+    // large-team launch (which returns at once if none was)
+    if (ev)
+        ev->large = true;
+    err = record(ev ? ev->large_begin : nullptr, st);
+    if (err == hipSuccess)
+        err = launch_large<MV, DEBUG>(A, st);
+    if (err == hipSuccess)
+        err = record(ev ? ev->large_end : nullptr, st);
     return err;
 }
 
-template <bool DEBUG>
+template <bool MV, bool DEBUG>
 static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStream_t st, LaunchEvents *ev)
 {
     switch (s.waves_per_team * 10000 + s.track_capacity) {
-    case 10256: return launch_pair<1, 256, DEBUG>(A, s, st, ev);
-    case 10512: return launch_pair<1, 512, DEBUG>(A, s, st, ev);
-    case 11024: return launch_pair<1, 1024, DEBUG>(A, s, st, ev);
-    case 20256: return launch_pair<2, 256, DEBUG>(A, s, st, ev);
-    case 20512: return launch_pair<2, 512, DEBUG>(A, s, st, ev);
-    case 21024: return launch_pair<2, 1024, DEBUG>(A, s, st, ev);
-    case 40256: return launch_pair<4, 256, DEBUG>(A, s, st, ev);
-    case 40512: return launch_pair<4, 512, DEBUG>(A, s, st, ev);
-    case 41024: return launch_pair<4, 1024, DEBUG>(A, s, st, ev);
+    case 10256: return launch_pair<1, 256, MV, DEBUG>(A, st, ev);
+    case 10512: return launch_pair<1, 512, MV, DEBUG>(A, st, ev);
+    case 11024: return launch_pair<1, 1024, MV, DEBUG>(A, st, ev);
+    case 20256: return launch_pair<2, 256, MV, DEBUG>(A, st, ev);
+    case 20512: return launch_pair<2, 512, MV, DEBUG>(A, st, ev);
+    case 21024: return launch_pair<2, 1024, MV, DEBUG>(A, st, ev);
+    case 40256: return launch_pair<4, 256, MV, DEBUG>(A, st, ev);
+    case 40512: return launch_pair<4, 512, MV, DEBUG>(A, st, ev);
+    case 41024: return launch_pair<4, 1024, MV, DEBUG>(A, st, ev);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1102,7 +1418,12 @@ static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStrea
 int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return (int)(debug ? launch_dispatch<true>(args, s, st, ev) : launch_dispatch<false>(args, s, st, ev));
+    hipError_t err;
+    if (args.p.mv)
+        err = debug ? launch_dispatch<true, true>(args, s, st, ev) : launch_dispatch<true, false>(args, s, st, ev);
+    else
+        err = debug ? launch_dispatch<false, true>(args, s, st, ev) : launch_dispatch<false, false>(args, s, st, ev);
+    return (int)err;
 }
 
 }  // namespace pvk

@@ -48,6 +48,8 @@ class pv_params(ctypes.Structure):
         ("chi2_max", ctypes.c_float), ("conv_dchi2", ctypes.c_float), ("conv_dz", ctypes.c_float),
         ("max_rho_pp", ctypes.c_float), ("cond_fp64", ctypes.c_float), ("sing_ratio", ctypes.c_float),
         ("max_tracks_per_event", ctypes.c_int32), ("max_vertices_per_event", ctypes.c_int32),
+        ("assoc_mode", ctypes.c_int32), ("chi2_max_mv", ctypes.c_float), ("chi2_window_mv", ctypes.c_float),
+        ("conv_dz_mv", ctypes.c_float), ("dup_ratio", ctypes.c_float), ("w_count_mv", ctypes.c_float),
     ]
 
 

@@ -16,6 +16,15 @@ threshold may go the other way in binary32; such a vertex is a reported tie:
 its iteration count and weights are not compared, its position must still
 agree within TIE_POS_TOL_MM (one more or one less step moves it by less than
 the 1 micrometre convergence threshold).
+
+Multi-vertex variant (Eq. 18): the pre-cut is binary32 on both sides, so the
+candidates' list lengths are compared bit-exactly.  Three decisions follow a
+binary32 fit on the GPU and a binary64 fit in the oracle, and count as ties
+when the oracle took them within a margin: a vertex's track count may differ
+by the tracks whose oracle weight lies within 1e-4 of w_count_mv; an event's
+vertex count may differ when one of its vertices had such tracks or a
+duplicate test within 1 % of its threshold; a track may report another vertex
+when its weight there equals the oracle's best within W_TOL.
 """
 import dataclasses
 from typing import Dict, List
@@ -72,7 +81,7 @@ def _f32_bits(a):
 
 
 def compare(batch, g: "pv.HostResult", o: "oracle.OracleResult", debug: bool = False,
-            fit: bool = True) -> Report:
+            fit: bool = True, mv: bool = False) -> Report:
     """Compare everything; with fit=False only the stages defined bit-exactly
     (status, binary32 projection, histogram, clusters, association)."""
     r = Report(n_events=batch.n_events, n_tracks=batch.n_tracks)
@@ -126,7 +135,11 @@ def compare(batch, g: "pv.HostResult", o: "oracle.OracleResult", debug: bool = F
             continue
         ng, no = int(g.n_vertices[e]), int(o.n_vertices[e])
         if ng != no:
-            r.fail(f"event {e}: {ng} vertices on the GPU, {no} in the oracle")
+            ovs = o.vertices[e, :no]
+            if mv and no and (np.any(ovs["n_near"] > 0) or np.any(ovs["dup_margin"] < 1e-2)):
+                r.ties += 1
+            else:
+                r.fail(f"event {e}: {ng} vertices on the GPU, {no} in the oracle")
             continue
         r.n_vertices += no
         gv, ov = g.vertices[e, :no], o.vertices[e, :no]
@@ -134,8 +147,12 @@ def compare(batch, g: "pv.HostResult", o: "oracle.OracleResult", debug: bool = F
         for k in range(no):
             for f, of in (("bin_lo", "bin_lo"), ("bin_hi", "bin_hi"), ("peak_bin", "peak_bin"),
                           ("n_tracks", "n_tracks")):
-                if int(gv[k][f]) != int(ov[k][of]):
+                d = abs(int(gv[k][f]) - int(ov[k][of]))
+                allowed = int(ov[k]["n_near"]) if (mv and f == "n_tracks") else 0
+                if d > allowed:
                     r.fail(f"event {e} vertex {k}: {f} {int(gv[k][f])} vs {int(ov[k][of])}")
+                elif d:
+                    r.ties += 1
             tie = int(gv[k]["n_iter"]) != int(ov[k]["n_iter"])
             if tie:
                 if ov[k]["conv_margin"] < TIE_MARGIN:
@@ -173,8 +190,16 @@ def compare(batch, g: "pv.HostResult", o: "oracle.OracleResult", debug: bool = F
     for e in np.nonzero(valid_ev)[0]:
         if g.n_vertices[e] == o.n_vertices[e]:
             sel[batch.offsets[e]:batch.offsets[e + 1]] = True
-    if not np.array_equal(g.track_vertex[sel], o.track_vertex[sel]):
-        k = np.nonzero((g.track_vertex != o.track_vertex) & sel)[0][:5]
+    diff = (g.track_vertex != o.track_vertex) & sel
+    if mv and np.any(diff):
+        # another vertex of (within tolerance) the same, largest weight
+        same = diff & (np.abs(g.track_weight.astype(np.float64) - o.track_weight) < W_TOL) & \
+            (g.track_vertex >= 0) & (o.track_vertex >= 0)
+        r.ties += int(np.sum(same))
+        tie_tracks |= same
+        diff &= ~same
+    if np.any(diff):
+        k = np.nonzero(diff)[0][:5]
         r.fail(f"track vertex ids differ at tracks {k.tolist()}")
     cmp = sel & ~tie_tracks
     if np.any(cmp):

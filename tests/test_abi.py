@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(pv.pv_params) == 25 * 4
+    assert ctypes.sizeof(pv.pv_params) == 31 * 4
     assert pv.VERTEX_DTYPE.itemsize == 64 and pv.CLUSTER_DTYPE.itemsize == 32
     assert ctypes.sizeof(pv.pv_tracks) == 8 * 8
 
@@ -58,6 +58,17 @@ def test_defaults_match_paper_constants():
     assert p.conv_dchi2 == pytest.approx(vals["conv_dchi2"]) and p.conv_dz == pytest.approx(vals["conv_dz_mm"])
     assert p.max_rho_pp == pytest.approx(vals["max_rho_pp_mm"])
     assert pv.pv_nbins(p) == 4000
+    # GPU variant: the convergence threshold the paper prints for it
+    assert p.assoc_mode == 0 and p.conv_dz_mv == pytest.approx(vals["conv_dz_gpu_mm"])
+
+
+@pytest.mark.parametrize("field,value", [
+    ("chi2_max_mv", 0.0), ("chi2_max_mv", 200.0), ("chi2_window_mv", -1.0), ("conv_dz_mv", 0.0),
+    ("dup_ratio", -1.0), ("dup_ratio", float("inf")), ("w_count_mv", 1.5), ("w_count_mv", float("nan")),
+])
+def test_bad_multivertex_params_rejected(field, value):
+    assert _call(params=pv.make_params({"assoc_mode": 1, field: value})) == pv.PV_EINVAL
+    assert "params" in pv.pv_last_error()
 
 
 def test_nbins_rejects_fractional_ranges():
@@ -95,6 +106,7 @@ def test_null_pointers_rejected(null):
     ("frac_bits", 0), ("frac_bits", 19), ("max_vertices_per_event", 0), ("max_vertices_per_event", 129),
     ("max_tracks_per_event", 4097), ("max_iter", 0), ("chi2_max", 0.0), ("u0", -1.0), ("dip_prom", 0),
     ("proto_thr", -1), ("z_max", 400.3), ("sigma_max_pp", float("nan")), ("sing_ratio", 1.0),
+    ("assoc_mode", 2), ("assoc_mode", -1),
 ])
 def test_bad_params_rejected(field, value):
     assert _call(params=pv.make_params({field: value})) == pv.PV_EINVAL

@@ -1,0 +1,93 @@
+"""GPU parity of the multi-vertex variant (Sec. 3.5 and Sec. 5: every track
+weighted to every candidate with Eq. 18, chi2 pre-cut, |dz| convergence,
+duplicate rejection) against the oracle's same variant.  The pre-cut is
+binary32 on both sides and compared bit-exactly (candidate list lengths);
+decisions after the binary32 fit follow the tie rules of tests/parity.py."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from paper_2412_14966_amd import pvfind as pv, synth
+from test_gpu_parity import _exact_event, _spread_event
+
+pytestmark = pytest.mark.gpu
+
+MV = {"assoc_mode": 1}
+
+
+def say(msg):
+    print(f"[gpu-mv] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pv.lib()
+    yield
+
+
+def check(batch, params=None, schedule=None, debug=True, name="", max_tie_frac=0.01):
+    prm = dict(MV, **(params or {}))
+    p = pv.make_params(prm)
+    say(f"{name}: {batch.n_events} events, {batch.n_tracks} tracks, schedule={schedule}, debug={debug}")
+    g = pv.run(batch, prm, schedule=schedule, debug=debug)
+    o = oracle.find(batch, parity.oracle_params(p), debug=debug)
+    rep = parity.compare(batch, g, o, debug=debug, mv=True)
+    say(f"{name}: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+    assert rep.ties <= max(3, max_tie_frac * rep.n_vertices)
+    return g, o, rep
+
+
+def test_mv_config1_debug():
+    check(synth.generate("pp_mu5_100ev"), name="mv pp mu=5 100 events")
+
+
+def test_mv_full_size_bench_workload():
+    """10,000 events at mu = 5 in the benchmark's launch configuration."""
+    check(synth.generate("pp_mu5_10kev", keep_truth=False), debug=False, name="mv pp mu=5 10k events")
+
+
+def test_mv_beam_gas_and_high_pileup_samples():
+    check(synth.generate("pp_mu5_gas_50kev", n_events=3000, keep_truth=False), name="mv pp + beam-gas 3k")
+    check(synth.generate("pp_mu40_20kev", n_events=400, keep_truth=False), name="mv mu=40 400 events")
+
+
+@pytest.mark.parametrize("sched", [dict(waves_per_team=w, track_capacity=c, persistent=m, teams_per_cu=0)
+                                   for (w, c, m) in ((1, 256, 2), (2, 512, 4), (4, 1024, 2), (2, 1024, 4))],
+                         ids=lambda s: f"w{s['waves_per_team']}c{s['track_capacity']}m{s['persistent']}")
+def test_mv_schedules_and_deferrals(sched):
+    """Small teams hand the large-event launch the events whose tracks,
+    touched words, clusters or candidate lists exceed them: a 700-track
+    vertex, 34 vertices packed at the low end, 72 gas clusters."""
+    rng = np.random.default_rng(44)
+    evs = [_spread_event(np.linspace(-500, 300, 20), 6, rng),
+           _spread_event(-590.0 + 6.0 * np.arange(34), 5, rng),
+           _spread_event(-598.0 + 4.0 * np.arange(72), 4, rng),
+           _exact_event((0.0, 0.0, 5.0), 700, rng)]
+    b = synth.concat([synth.generate("pp_mu5_100ev", n_events=30), synth.from_tracks(evs)])
+    check(b, schedule=sched, name="mv schedules")
+
+
+def test_mv_candidate_lists_beyond_the_track_limit():
+    """An unbounded pre-cut puts every track in every candidate's list: events
+    whose lists exceed max_tracks_per_event are flagged and give no vertex,
+    the others still match the oracle."""
+    b = synth.generate("pp_mu5_100ev", n_events=40)
+    g, o, rep = check(b, {"chi2_window_mv": 1e30, "max_tracks_per_event": 1024}, name="mv lists over the limit")
+    assert np.any(o.status & oracle.EV_TOO_MANY_TRACKS)
+    assert np.any((o.status & oracle.EV_TOO_MANY_TRACKS) == 0)
+
+
+def test_mv_duplicates_and_open_selection():
+    """Duplicate rejection with a large ratio drops many candidates; with the
+    selection opened up every surviving fit is written."""
+    b = synth.generate("pp_mu40_20kev", n_events=100, keep_truth=False)
+    check(b, {"dup_ratio": 400.0}, name="mv duplicates R=400")
+    check(b, {"pv_min_pp": 0, "pv_min_gas": 0, "max_rho_pp": 1e9, "dup_ratio": 0.0}, name="mv open selection")
