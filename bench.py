@@ -235,6 +235,31 @@ def main():
                 "kernel": kname, "algorithmic_bytes_per_launch": abytes,
                 "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2)}
 
+    # the GPU variant of the association and fit (Eq. 18 weights over every
+    # candidate), same batch and schedule, same timing
+    mvp = pv.make_params({"assoc_mode": 1})
+    mv_args = (ctypes.byref(tr), offs, db.n_events, ctypes.byref(bl), ctypes.byref(mvp), ctypes.byref(ov),
+               ctypes.byref(ot), st)
+    for _ in range(args.warmup):
+        if L.pv_find(*mv_args) != 0:
+            raise RuntimeError(pv.pv_last_error())
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        L.pv_find(*mv_args)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / args.steps
+    pv.pv_timing_start()
+    for _ in range(args.steps):
+        L.pv_find(*mv_args)
+    mv_main_ms, mv_large_ms, mv_n = pv.pv_timing_stop()
+    multivertex = {"events_per_s": round(batch.n_events / (mv_ms / 1e3), 1), "ms_per_step": round(mv_ms, 5),
+                   "kernel_us": round(mv_main_ms / mv_n * 1e3, 2),
+                   "large_event_kernel_us": round(mv_large_ms / mv_n * 1e3, 2),
+                   "n_vertices": int(out.n_vertices.sum().item())}
+    log(f"multi-vertex variant: {mv_ms * 1e3:.1f} us per step, {multivertex['events_per_s']:.4g} events/s")
+
     # plain form: one pv_find launch per event on the same stream
     n_pe = min(args.per_event_sample, batch.n_events)
     mv = params.max_vertices_per_event
@@ -296,7 +321,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
                    "n_vertices": nv, "schedule": schedule},
-        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event, "served": served,
+        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event, "multivertex": multivertex,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 
