@@ -49,6 +49,7 @@ class OrcParams(ctypes.Structure):
         ("max_tracks", ctypes.c_int), ("max_vertices", ctypes.c_int),
         ("assoc_mode", ctypes.c_int), ("chi2_max_mv", ctypes.c_double), ("chi2_window_mv", ctypes.c_double),
         ("conv_dz_mv", ctypes.c_double), ("dup_ratio", ctypes.c_double), ("w_count_mv", ctypes.c_double),
+        ("peak_mode", ctypes.c_int),
     ]
 
 

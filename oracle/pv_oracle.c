@@ -80,6 +80,7 @@ void orc_params_default(orc_params *p)
     p->conv_dz_mv = 0.0005;          /* Sec. 3.5, GPU criterion: 0.5 micrometre */
     p->dup_ratio = 25.0;
     p->w_count_mv = 0.5;
+    p->peak_mode = ORC_PEAK_Z_ORDERED;
 }
 
 int orc_nbins(const orc_params *p)
@@ -291,6 +292,100 @@ double orc_seed_z(const int *h, int nb, int i, const orc_params *p)
  * to the proto-cluster's end both reach the cluster-integral threshold of
  * their region.  The remainder is a cluster if it reaches the threshold.
  */
+/* significant minima of bins [s, e] in z order (reading: a minimum counts
+   after a fall of at least D below the preceding maximum and a rise of at
+   least D above it; of a flat minimum the lowest-z bin is kept) */
+static int dip_minima(const int *h, int s, int e, int D, int *minima)
+{
+    int n_min = 0, up = 1, M = h[s], m = 0, mj = -1, k;
+    for (k = s + 1; k <= e; ++k) {
+        if (up) {
+            if (h[k] > M) {
+                M = h[k];
+            } else if (h[k] <= M - D) {
+                up = 0;
+                m = h[k];
+                mj = k;
+            }
+        } else {
+            if (h[k] < m) {
+                m = h[k];
+                mj = k;
+            } else if (h[k] >= m + D) {
+                minima[n_min++] = mj;
+                up = 1;
+                M = h[k];
+            }
+        }
+    }
+    return n_min;
+}
+
+static void emit_cluster(const int *h, int lo, int hi, const orc_params *p, int nb, orc_cluster *out, int max_out,
+                         int *n_out, int *overflow)
+{
+    if (*n_out < max_out) {
+        orc_cluster *cl = &out[*n_out];
+        memset(cl, 0, sizeof(*cl));
+        cl->lo = lo;
+        cl->hi = hi;
+        cl->peak = first_argmax(h, lo, hi);
+        cl->z_seed = orc_seed_z(h, nb, cl->peak, p);
+        cl->kept = 1;
+        ++*n_out;
+    } else {
+        *overflow = 1;
+    }
+}
+
+/*
+ * x86 variant of the splitting (Sec. 3.3): the range [s, e] is cut at the
+ * smallest significant minimum between its two largest maxima, and each part
+ * is treated the same way, recursively (its significant extrema found anew
+ * within the part).  Readings: the maxima are the highest bins of the
+ * segments between consecutive significant minima; of equal maxima the lower
+ * z counts as larger, of equal minima the lower z is taken; the cut bin stays
+ * with the left part; a cut is made only when both parts reach the integral
+ * threshold of their region (Table 2), otherwise the range is one cluster if
+ * it reaches its own.  Clusters come out in z order.
+ */
+static void split_recursive(const int *h, int s, int e, const orc_params *p, int nb, orc_cluster *out,
+                            int max_out, int *n_out, int *overflow)
+{
+    int *minima = (int *)malloc(sizeof(int) * (size_t)(e - s + 1));
+    const int n_min = dip_minima(h, s, e, p->dip_prom, minima);
+    int cut = -1;
+    if (n_min > 0) {
+        /* the two largest segment maxima */
+        int b1 = -1, b2 = -1, q;
+        for (q = 0; q <= n_min; ++q) {
+            const int a = (q == 0) ? s : minima[q - 1] + 1;
+            const int b = (q == n_min) ? e : minima[q] - 1;
+            const int i = first_argmax(h, a, b);
+            if (b1 < 0 || h[i] > h[b1]) {
+                b2 = b1;
+                b1 = i;
+            } else if (b2 < 0 || h[i] > h[b2]) {
+                b2 = i;
+            }
+        }
+        const int p1 = b1 < b2 ? b1 : b2, p2 = b1 < b2 ? b2 : b1;
+        for (q = 0; q < n_min; ++q)
+            if (minima[q] > p1 && minima[q] < p2 && (cut < 0 || h[minima[q]] < h[cut]))
+                cut = minima[q];
+        if (cut >= 0 && !(range_sum(h, s, cut) >= integral_threshold(h, s, cut, p) &&
+                          range_sum(h, cut + 1, e) >= integral_threshold(h, cut + 1, e, p)))
+            cut = -1;
+    }
+    free(minima);
+    if (cut >= 0) {
+        split_recursive(h, s, cut, p, nb, out, max_out, n_out, overflow);
+        split_recursive(h, cut + 1, e, p, nb, out, max_out, n_out, overflow);
+    } else if (range_sum(h, s, e) >= integral_threshold(h, s, e, p)) {
+        emit_cluster(h, s, e, p, nb, out, max_out, n_out, overflow);
+    }
+}
+
 int orc_peak_search(const int *h, const orc_params *p, orc_cluster *out,
                     int max_out, int *overflow)
 {
@@ -310,30 +405,13 @@ int orc_peak_search(const int *h, const orc_params *p, orc_cluster *out,
         const int e = j;
         ++j;
 
-        /* dip search */
-        int n_min = 0, up = 1, M = h[s], m = 0, mj = -1, k;
-        for (k = s + 1; k <= e; ++k) {
-            if (up) {
-                if (h[k] > M) {
-                    M = h[k];
-                } else if (h[k] <= M - D) {
-                    up = 0;
-                    m = h[k];
-                    mj = k;
-                }
-            } else {
-                if (h[k] < m) {
-                    m = h[k];
-                    mj = k;
-                } else if (h[k] >= m + D) {
-                    minima[n_min++] = mj;
-                    up = 1;
-                    M = h[k];
-                }
-            }
+        if (p->peak_mode == ORC_PEAK_RECURSIVE) {
+            split_recursive(h, s, e, p, nb, out, max_out, &n_out, overflow);
+            continue;
         }
+        const int n_min = dip_minima(h, s, e, D, minima);
 
-        /* z-ordered splitting */
+        /* z-ordered splitting (GPU variant) */
         int cs = s, q, lo = 0, hi = 0;
         for (q = 0; q <= n_min; ++q) {
             int emit = 0;
@@ -351,20 +429,8 @@ int orc_peak_search(const int *h, const orc_params *p, orc_cluster *out,
                 hi = e;
                 emit = 1;
             }
-            if (!emit)
-                continue;
-            if (n_out < max_out) {
-                orc_cluster *cl = &out[n_out];
-                memset(cl, 0, sizeof(*cl));
-                cl->lo = lo;
-                cl->hi = hi;
-                cl->peak = first_argmax(h, lo, hi);
-                cl->z_seed = orc_seed_z(h, nb, cl->peak, p);
-                cl->kept = 1;
-                ++n_out;
-            } else {
-                *overflow = 1;
-            }
+            if (emit)
+                emit_cluster(h, lo, hi, p, nb, out, max_out, &n_out, overflow);
         }
     }
     free(minima);

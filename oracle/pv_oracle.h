@@ -66,7 +66,13 @@ typedef struct {
     double conv_dz_mv;        /* GPU convergence: |dz| below this, no dchi2 requirement */
     double dup_ratio;         /* duplicates: dz^2 / (Czz_1 + Czz_2) below this */
     double w_count_mv;        /* a track counts for a vertex with final weight >= this */
+    /* splitting of proto-clusters (Sec. 3.3) */
+    int    peak_mode;         /* 0: minima in z order (GPU variant); 1: the smallest minimum
+                                 between the two largest maxima, recursively (x86 variant) */
 } orc_params;
+
+#define ORC_PEAK_Z_ORDERED 0
+#define ORC_PEAK_RECURSIVE 1
 
 #define ORC_ASSOC_PARTITION   0
 #define ORC_ASSOC_MULTIVERTEX 1

@@ -1009,3 +1009,118 @@ def test_mv_candidate_lists_share_the_track_capacity():
             r2 = oracle.find(b.select([e]), {"assoc_mode": 1, "chi2_window_mv": 1e300, "max_tracks": cap})
             assert bool(r2.status[0] & oracle.EV_TOO_MANY_TRACKS) == flagged
             assert (r2.n_vertices[0] == 0) or not flagged
+
+
+# --------------------------------------------------------------------------
+# x86 variant of the splitting (Sec. 3.3): recursive, at the smallest minimum
+# between the two largest maxima
+# --------------------------------------------------------------------------
+def _naive_recursive_peaks(h, p, gas_bin):
+    """Test-only re-formulation: proto-clusters, then for each range its
+    significant minima (same hysteresis), the segment maxima between them,
+    the two largest (lower z first on ties), the smallest minimum between
+    them (lower z on ties), a cut if both parts reach their thresholds, and
+    the same on each part."""
+    T, D = p["proto_thr"], p["dip_prom"]
+
+    def thr(a, b):
+        seg = list(h[a:b + 1])
+        i = a + seg.index(max(seg))
+        return p["min_int_gas"] if i < gas_bin else p["min_int_pp"]
+
+    def minima_of(s, e):
+        mins, state, ref, pos = [], "up", h[s], None
+        for j in range(s + 1, e + 1):
+            v = h[j]
+            if state == "up":
+                if v > ref:
+                    ref = v
+                elif ref - v >= D:
+                    state, ref, pos = "down", v, j
+            else:
+                if v < ref:
+                    ref, pos = v, j
+                elif v - ref >= D:
+                    mins.append(pos)
+                    state, ref = "up", v
+        return mins
+
+    def split(s, e, out):
+        mins = minima_of(s, e)
+        cut = None
+        if mins:
+            bounds = [s] + [m + 1 for m in mins]
+            ends = [m - 1 for m in mins] + [e]
+            peaks = []
+            for a, b in zip(bounds, ends):
+                seg = list(h[a:b + 1])
+                peaks.append((-int(max(seg)), a + seg.index(max(seg))))
+            peaks.sort()
+            p1, p2 = sorted([peaks[0][1], peaks[1][1]])
+            inside = [(int(h[m]), m) for m in mins if p1 < m < p2]
+            if inside:
+                c = min(inside)[1]
+                if sum(h[s:c + 1]) >= thr(s, c) and sum(h[c + 1:e + 1]) >= thr(c + 1, e):
+                    cut = c
+        if cut is not None:
+            split(s, cut, out)
+            split(cut + 1, e, out)
+        elif sum(h[s:e + 1]) >= thr(s, e):
+            out.append((s, e))
+
+    out = []
+    j, nb = 0, len(h)
+    while j < nb:
+        if h[j] <= T:
+            j += 1
+            continue
+        s = j
+        while j + 1 < nb and h[j + 1] > T:
+            j += 1
+        split(s, j, out)
+        j += 1
+    return out
+
+
+def test_recursive_splitting_matches_naive_formulation():
+    p = oracle.default_params()
+    gb = oracle.gas_bin()
+    rng = np.random.default_rng(45)
+    multi = 0
+    for trial in range(600):
+        h = np.zeros(4000, dtype=np.int32)
+        start = int(rng.choice([40, 1180, 2000, 3900]))
+        if trial % 2:
+            n = int(rng.integers(1, 60))
+            scale = int(rng.choice([3000, 60000, 400000]))
+            h[start:start + n] = rng.integers(0, scale, n)
+        else:   # a few peaks of random heights and widths, close together
+            x = np.arange(80)
+            f = np.full(80, 0.2)
+            c = 5.0
+            for _ in range(int(rng.integers(2, 6))):
+                f += rng.uniform(0.5, 12) * np.exp(-0.5 * ((x - c) / rng.uniform(0.6, 2.5)) ** 2)
+                c += rng.uniform(3, 9)
+            h[start:start + 80] = (f * 65536 * rng.uniform(0.9, 1.1, 80)).astype(np.int32)
+        got, ov = oracle.peak_search(h, {"peak_mode": 1})
+        ref = _naive_recursive_peaks(h, p, gb)
+        assert [(int(c["lo"]), int(c["hi"])) for c in got] == ref
+        for c in got:
+            assert c["peak"] == c["lo"] + int(np.argmax(h[c["lo"]:c["hi"] + 1]))
+        multi += len(ref) > 2
+    assert multi > 100   # many ranges with several cuts
+
+
+def test_recursive_and_z_ordered_splitting_hand_case():
+    """Peaks A (10 tracks), B (2.2), C (10) with minima of 0.15 (A|B) and 0.12
+    (B|C) tracks, all significant.  The z-ordered split cuts at A|B (both
+    sides reach 2.5 tracks) and cannot cut B (2.32 tracks) off C: [A], [B C].
+    The recursive split cuts at the smallest minimum between the two largest
+    maxima (B|C), then cannot cut B off A: [A B], [C]."""
+    U_ = 65536
+    vals = [U_, 10 * U_, int(0.15 * U_), int(2.2 * U_), int(0.12 * U_), 10 * U_, U_]
+    h = _hist_from(vals)
+    zo, _ = oracle.peak_search(h)
+    rc, _ = oracle.peak_search(h, {"peak_mode": 1})
+    assert [(int(c["lo"]) - 2000, int(c["hi"]) - 2000) for c in zo] == [(0, 2), (3, 6)]
+    assert [(int(c["lo"]) - 2000, int(c["hi"]) - 2000) for c in rc] == [(0, 4), (5, 6)]
