@@ -117,10 +117,18 @@ typedef struct {
     float   conv_dz_mv;                /* mm                                           */
     float   dup_ratio;
     float   w_count_mv;
+    /* Splitting of proto-clusters (Sec. 3.3).  PV_PEAK_Z_ORDERED (default, the
+     * GPU variant): significant minima taken in z order.  PV_PEAK_RECURSIVE
+     * (the x86 variant): the smallest significant minimum between the two
+     * largest maxima, then each part the same way; ties go to the lower z, a
+     * cut needs both parts to reach their integral threshold.                */
+    int32_t peak_mode;
 } pv_params;
 
 #define PV_ASSOC_PARTITION   0
 #define PV_ASSOC_MULTIVERTEX 1
+#define PV_PEAK_Z_ORDERED    0
+#define PV_PEAK_RECURSIVE    1
 
 /* One fitted vertex, 64 bytes. */
 typedef struct {

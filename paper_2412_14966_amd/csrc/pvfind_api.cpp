@@ -148,6 +148,8 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
          !(p->w_count_mv >= 0.0f) || !(p->w_count_mv <= 1.0f)))
         return fail(PV_EINVAL, "params: chi2_max_mv in (0, 170), chi2_window_mv >= 0, conv_dz_mv > 0, finite "
                                "dup_ratio >= 0 and w_count_mv in [0, 1] required");
+    if (p->peak_mode != PV_PEAK_Z_ORDERED && p->peak_mode != PV_PEAK_RECURSIVE)
+        return fail(PV_EINVAL, "params: peak_mode must be PV_PEAK_Z_ORDERED or PV_PEAK_RECURSIVE");
     if (!std::isfinite(bl->x) || !std::isfinite(bl->y) || !std::isfinite(bl->tx) || !std::isfinite(bl->ty))
         return fail(PV_EINVAL, "beamline: non-finite value");
     k.z_min = p->z_min;
@@ -189,6 +191,7 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
     k.conv_dz_mv = p->conv_dz_mv;
     k.dup_ratio = p->dup_ratio;
     k.w_count_mv = p->w_count_mv;
+    k.peak_rec = p->peak_mode == PV_PEAK_RECURSIVE ? 1 : 0;
     return PV_OK;
 }
 
@@ -381,6 +384,7 @@ void pv_params_default(pv_params *p)
     p->conv_dz_mv = 0.0005f;       // Sec. 3.5, GPU criterion: 0.5 micrometre
     p->dup_ratio = 25.0f;
     p->w_count_mv = 0.5f;
+    p->peak_mode = PV_PEAK_Z_ORDERED;
 }
 
 int32_t pv_nbins(const pv_params *p)

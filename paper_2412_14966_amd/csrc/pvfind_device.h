@@ -429,6 +429,158 @@ __device__ __forceinline__ void write_walk(const WalkOut &o, int s, int e, short
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sec. 3.3, x86 variant: a range is cut at the smallest significant minimum
+// between its two largest maxima, and each part the same way, recursively
+// (its extrema found anew within the part).  The maxima are the highest bins
+// of the segments between consecutive significant minima; of equal maxima the
+// lower z counts as larger, of equal minima the lower z is taken; the cut bin
+// stays with the left part; a cut needs both parts to reach the integral
+// threshold of their region.  h[k + off] is bin k.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int thr_of(int peak, const KParams &p)
+{
+    return (peak < p.gas_bin) ? p.min_int_gas : p.min_int_pp;
+}
+
+// cut bin of [lo, hi], or -1
+__device__ __forceinline__ int recursive_cut(const int *h, int off, const KParams &p, int lo, int hi)
+{
+    // walk 1: the two largest segment maxima
+    int up = 1, M = 0, m = 0, mj = lo;
+    int segM = INT_MIN, segI = lo, aM = INT_MIN, aI = lo;
+    int b1M = INT_MIN, b1I = -1, b2M = INT_MIN, b2I = -1, nseg = 0;
+    for (int k = lo; k <= hi + 1; ++k) {
+        if (k == hi + 1) {   // close the last segment
+            ++nseg;
+            const bool top = segM > b1M;
+            const bool second = !top && segM > b2M;
+            b2M = top ? b1M : (second ? segM : b2M);
+            b2I = top ? b1I : (second ? segI : b2I);
+            b1M = top ? segM : b1M;
+            b1I = top ? segI : b1I;
+            break;
+        }
+        const int hk = h[k + off];
+        if (k == lo) {
+            M = hk;
+            segM = hk;
+            segI = k;
+        } else if (up) {
+            if (hk > M)
+                M = hk;
+            if (hk > segM) {
+                segM = hk;
+                segI = k;
+            }
+            if (hk <= M - p.dip_prom) {
+                up = 0;
+                m = hk;
+                mj = k;
+                aM = INT_MIN;
+            }
+        } else if (hk < m) {
+            m = hk;
+            mj = k;
+            aM = INT_MIN;
+        } else if (hk >= m + p.dip_prom) {
+            ++nseg;
+            const bool top = segM > b1M;
+            const bool second = !top && segM > b2M;
+            b2M = top ? b1M : (second ? segM : b2M);
+            b2I = top ? b1I : (second ? segI : b2I);
+            b1M = top ? segM : b1M;
+            b1I = top ? segI : b1I;
+            // the new segment: bins (mj, k]
+            segM = aM;
+            segI = aI;
+            if (hk > segM) {
+                segM = hk;
+                segI = k;
+            }
+            up = 1;
+            M = hk;
+        } else if (hk > aM) {
+            aM = hk;
+            aI = k;
+        }
+    }
+    if (nseg < 2)
+        return -1;
+    const int p1 = min(b1I, b2I), p2 = max(b1I, b2I);
+    // walk 2: the smallest significant minimum strictly between them
+    int cut = -1, cutv = INT_MAX;
+    up = 1;
+    for (int k = lo; k <= p2; ++k) {
+        const int hk = h[k + off];
+        if (k == lo) {
+            M = hk;
+        } else if (up) {
+            if (hk > M) {
+                M = hk;
+            } else if (hk <= M - p.dip_prom) {
+                up = 0;
+                m = hk;
+                mj = k;
+            }
+        } else if (hk < m) {
+            m = hk;
+            mj = k;
+        } else if (hk >= m + p.dip_prom) {
+            if (mj > p1 && mj < p2 && m < cutv) {
+                cut = mj;
+                cutv = m;
+            }
+            up = 1;
+            M = hk;
+        }
+    }
+    if (cut < 0)
+        return -1;
+    if (sum_bins(h, off, lo, cut) < thr_of(argmax_bins(h, off, lo, cut), p) ||
+        sum_bins(h, off, cut + 1, hi) < thr_of(argmax_bins(h, off, cut + 1, hi), p))
+        return -1;
+    return cut;
+}
+
+// Clusters of proto-cluster [s, e] in z order: each leaf is found by
+// descending from the whole range towards the first bin not yet covered (no
+// stack: the cuts are recomputed, each step shrinks the range, and each leaf
+// advances the position).  With WRITE they go to clo / chi / cpk from index
+// `first` (below `cap`).  Returns their number.
+template <bool WRITE>
+__device__ __forceinline__ int walk_recursive(const int *h, int off, const KParams &p, int s, int e, short *clo,
+                                              short *chi, short *cpk, int cap, int first)
+{
+    int count = 0;
+    for (int pos = s; pos <= e;) {
+        int lo = s, hi = e;
+        for (;;) {
+            const int cut = recursive_cut(h, off, p, lo, hi);
+            if (cut < 0)
+                break;
+            if (pos <= cut)
+                hi = cut;
+            else
+                lo = cut + 1;
+        }
+        const int pk = argmax_bins(h, off, lo, hi);
+        if (sum_bins(h, off, lo, hi) >= thr_of(pk, p)) {
+            if (WRITE) {
+                const int q = first + count;
+                if (q < cap) {
+                    clo[q] = (short)lo;
+                    chi[q] = (short)hi;
+                    cpk[q] = (short)pk;
+                }
+            }
+            ++count;
+        }
+        pos = hi + 1;
+    }
+    return count;
+}
+
 // centre of bin i, z_i of Eq. 4; the fit's frame is anchored there because
 // z_i is exact in binary32 for the usual ranges while z_seed is not
 __device__ __forceinline__ float bin_centre(int i, const KParams &p)

@@ -35,6 +35,7 @@ struct KParams {
     int mv;
     float e_max_mv;             // exp(-chi2_max_mv / 2)
     float chi2_window_mv, conv_dz_mv, dup_ratio, w_count_mv;
+    int peak_rec;               // x86 splitting of proto-clusters (Sec. 3.3)
 };
 
 // Device workspace of one stream: work-queue counters, the list of events

@@ -209,16 +209,25 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP, BIG, MV> &S, const KPar
                 e = S.pe[lane];
                 off = S.po[lane];
             }
-            const int tot = has ? sum_bins(h, off, s, e) : 0;
-            WalkOut wo{{0u, 0u, 0u, 0u}, 0, -1};
-            const int c = has ? walk_proto<false>(h, off, p, s, e, tot, wo, nullptr, nullptr, nullptr, 0, 0) : 0;
-            const int incl = wave_incl_scan(c, lane);
-            const int first = n_found + incl - c;
-            if (has && wo.nsplit > 4)   // rare: more splits than recorded
-                walk_proto<true>(h, off, p, s, e, tot, wo, S.clo, S.chi, S.cpk, cap, first);
-            else if (has)
-                write_walk(wo, s, e, S.clo, S.chi, S.cpk, cap, first);
-            n_found += __shfl(incl, 63);
+            if (p.peak_rec) {
+                // x86 variant: count, then write from this lane's first index
+                const int c = has ? walk_recursive<false>(h, off, p, s, e, nullptr, nullptr, nullptr, 0, 0) : 0;
+                const int incl = wave_incl_scan(c, lane);
+                if (has && c > 0)
+                    walk_recursive<true>(h, off, p, s, e, S.clo, S.chi, S.cpk, cap, n_found + incl - c);
+                n_found += __shfl(incl, 63);
+            } else {
+                const int tot = has ? sum_bins(h, off, s, e) : 0;
+                WalkOut wo{{0u, 0u, 0u, 0u}, 0, -1};
+                const int c = has ? walk_proto<false>(h, off, p, s, e, tot, wo, nullptr, nullptr, nullptr, 0, 0) : 0;
+                const int incl = wave_incl_scan(c, lane);
+                const int first = n_found + incl - c;
+                if (has && wo.nsplit > 4)   // rare: more splits than recorded
+                    walk_proto<true>(h, off, p, s, e, tot, wo, S.clo, S.chi, S.cpk, cap, first);
+                else if (has)
+                    write_walk(wo, s, e, S.clo, S.chi, S.cpk, cap, first);
+                n_found += __shfl(incl, 63);
+            }
             npend = 0;
             __builtin_amdgcn_wave_barrier();
         }

@@ -50,6 +50,7 @@ class pv_params(ctypes.Structure):
         ("max_tracks_per_event", ctypes.c_int32), ("max_vertices_per_event", ctypes.c_int32),
         ("assoc_mode", ctypes.c_int32), ("chi2_max_mv", ctypes.c_float), ("chi2_window_mv", ctypes.c_float),
         ("conv_dz_mv", ctypes.c_float), ("dup_ratio", ctypes.c_float), ("w_count_mv", ctypes.c_float),
+        ("peak_mode", ctypes.c_int32),
     ]
 
 

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(pv.pv_params) == 31 * 4
+    assert ctypes.sizeof(pv.pv_params) == 32 * 4
     assert pv.VERTEX_DTYPE.itemsize == 64 and pv.CLUSTER_DTYPE.itemsize == 32
     assert ctypes.sizeof(pv.pv_tracks) == 8 * 8
 
@@ -106,7 +106,7 @@ def test_null_pointers_rejected(null):
     ("frac_bits", 0), ("frac_bits", 19), ("max_vertices_per_event", 0), ("max_vertices_per_event", 129),
     ("max_tracks_per_event", 4097), ("max_iter", 0), ("chi2_max", 0.0), ("u0", -1.0), ("dip_prom", 0),
     ("proto_thr", -1), ("z_max", 400.3), ("sigma_max_pp", float("nan")), ("sing_ratio", 1.0),
-    ("assoc_mode", 2), ("assoc_mode", -1),
+    ("assoc_mode", 2), ("assoc_mode", -1), ("peak_mode", 2), ("peak_mode", -1),
 ])
 def test_bad_params_rejected(field, value):
     assert _call(params=pv.make_params({field: value})) == pv.PV_EINVAL
