@@ -83,8 +83,11 @@ def served_leg(pv, synth, n_events):
     hw = pv.HostEvents(warm, params.max_vertices_per_event)
     with pv.Server(params, batch.beamline, cfg) as srv:
         srv.replay(hw, np.zeros(warm.n_events, dtype=np.int64))   # warm-up
-        comp = srv.replay(host, np.zeros(n_events, dtype=np.int64))
-        cap = latency_summary(comp)["achieved_events_per_s"]
+        # capacity: all events at once, the median of three replays (a single
+        # replay of ~30 ms varies by tens of percent)
+        caps = [latency_summary(srv.replay(host, np.zeros(n_events, dtype=np.int64)))["achieved_events_per_s"]
+                for _ in range(3)]
+        cap = float(np.median(caps))
         log(f"served capacity (all {n_events} events at once): {cap:.4g} events/s")
         out["capacity_events_per_s"] = cap
         # one untimed pass over the rates first: in the first ~0.2 s of a

@@ -91,3 +91,11 @@ def test_mv_duplicates_and_open_selection():
     b = synth.generate("pp_mu40_20kev", n_events=100, keep_truth=False)
     check(b, {"dup_ratio": 400.0}, name="mv duplicates R=400")
     check(b, {"pv_min_pp": 0, "pv_min_gas": 0, "max_rho_pp": 1e9, "dup_ratio": 0.0}, name="mv open selection")
+
+
+def test_mv_tilted_offset_beamline_and_slope_covariance():
+    """Kalman-like covariances with slope terms (Eq. 2 at the seed) and a
+    displaced, tilted beamline."""
+    b = synth.generate("pp_mu5_100ev", beamline=(1.092, 0.472, 2e-4, -1e-4), slope_cov=True)
+    check(b, name="mv offset tilted beamline, slope covariance")
+    check(b, {"peak_mode": 1}, name="mv + recursive splitting, offset tilted beamline")
