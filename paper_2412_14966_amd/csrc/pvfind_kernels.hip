@@ -47,7 +47,7 @@ struct VertexFit {
 };
 
 constexpr int kPages = 20;          // touched 64-bin histogram words a small team holds
-constexpr int kSmallVertices = 64;  // clusters a small team holds
+constexpr int kSmallVertices = 48;  // clusters a small team of up to 512 tracks holds (64 above)
 
 // LDS of one team.  Large-event teams hold the whole histogram.  Small teams
 // hold only the touched 64-bin words ("pages"): word w lives in page
@@ -57,7 +57,7 @@ constexpr int kSmallVertices = 64;  // clusters a small team holds
 // kSmallVertices clusters go to the large-team launch.
 template <int W, int CAP, bool BIG, bool MV>
 struct __align__(16) Smem {
-    static constexpr int V = BIG ? kMaxVertices : kSmallVertices;
+    static constexpr int V = BIG ? kMaxVertices : (CAP <= 512 ? kSmallVertices : 64);
     union {
         int hist[BIG ? kMaxBins : 1];
         struct {
@@ -1263,8 +1263,18 @@ __global__ __launch_bounds__(64 * kBigWaves) void pv_find_large(KArgs A)
 // capacity when the count is read from device memory).  Without a persistent
 // loop no value has to live from one event to the next, which keeps the
 // register footprint low.
+// Wavefronts per SIMD that the teams fitting a CU by LDS give, at most 6: the
+// register budget the compiler is held to (the second launch bound).
+template <int W, int CAP, bool MV>
+constexpr int small_waves_per_simd()
+{
+    constexpr int teams = (160 * 1024) / (int)sizeof(Smem<W, CAP, false, MV>);
+    constexpr int waves = teams * W / 4;
+    return waves < 1 ? 1 : (waves > 6 ? 6 : waves);
+}
+
 template <int W, int CAP, bool MV, bool DEBUG>
-__global__ __launch_bounds__(64 * W) void pv_find_single(KArgs A)
+__global__ __launch_bounds__(64 * W, (small_waves_per_simd<W, CAP, MV>())) void pv_find_single(KArgs A)
 {
     __shared__ Smem<W, CAP, false, MV> S;
     const int n_events = A.n_events_dev ? *A.n_events_dev : A.n_events;
