@@ -165,3 +165,22 @@ def test_autotune_picks_a_schedule_and_keeps_results(tmp_path):
                                                                     best["track_capacity"], best["persistent"])
     finally:
         pv.lib().pv_set_schedule(pv.ctypes.byref(old))
+
+
+@pytest.mark.parametrize("extra", [{"assoc_mode": 1}, {"peak_mode": 1}, {"assoc_mode": 1, "peak_mode": 1}],
+                         ids=["multivertex", "recursive", "both"])
+def test_served_variants_equal_batched(extra):
+    """The association and splitting variants through the server (graphs,
+    several streams): results equal the batched launch bit for bit."""
+    batch = synth.generate("served_mulog_200kev", n_events=1500, keep_truth=False)
+    params = pv.make_params(dict({"max_vertices_per_event": 96}, **extra))
+    say(f"served variant {extra}: {batch.n_events} events, {batch.n_tracks} tracks")
+    ref = pv.run(batch, pv.params_dict(params))
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=256, max_tracks_per_batch=256 * 600, n_slots=4,
+                                      n_streams=2, max_wait_us=100, use_graphs=1)
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, poisson_offsets(batch.n_events, 2.0e5, seed=5))
+        st = srv.stats()
+    assert st["completed"] == batch.n_events and st["batches"] > 1
+    check_same_as_batched(batch, host, ref, comp, params.max_vertices_per_event)
