@@ -202,7 +202,8 @@ typedef struct {
                                           they did not finish on the GPU, for a reason
                                           not found.  Large-event teams always run
                                           persistent.                                 */
-    int32_t teams_per_cu;              /* persistent grid size per compute unit        */
+    int32_t teams_per_cu;              /* 0..64, not used by modes 2 and 4 (it sized the
+                                          persistent grids of modes 1 and 3)           */
 } pv_schedule;
 
 /* Fill *p with the defaults described above. */

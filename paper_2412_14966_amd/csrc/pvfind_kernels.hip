@@ -368,8 +368,9 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
 
 // Final weights at the fitted position (Tukey, or Eq. 18 for the multi-vertex
 // variant), per-track outputs, chi2 and ndof (2 sum w - 3), covariance
-// (Eq. 14) and the vertex record.  Multi-vertex: a track may sit in several
-// candidates' lists; each written vertex offers it (weight, vertex) through an
+// (Eq. 14) and the vertex record.  Multi-vertex: the weights and chi2 were
+// stored by the counting pass at the same positions; a track may sit in
+// several candidates' lists, and each written vertex offers it (weight, vertex) through an
 // LDS maximum over keys (top 24 bits of the weight, then the lower vertex
 // index), and the winning slot writes the track's outputs.
 template <int W, int CAP, bool BIG, bool MV>
@@ -382,6 +383,10 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG, MV> &S, const KArgs
     const int tid = threadIdx.x;
     const int gid = tid >> lg, gl = tid & (L - 1);
     auto weight_at = [&](int sl, float dx, float dy, float dz, float &chi2) __attribute__((always_inline)) -> float {
+        if constexpr (MV) {   // stored by the counting pass at the final position
+            chi2 = S.u.f.X[sl];
+            return S.u.f.OTH[sl];
+        }
         const float wt = S.u.f.WT[sl];
         float w = 0.0f;
         chi2 = 0.0f;
@@ -389,9 +394,7 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG, MV> &S, const KArgs
             const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
             const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
             chi2 = wt * fmaf(rx, rx, ry * ry);
-            if constexpr (MV) {
-                w = mv_weight(chi2, S.u.f.OTH[sl], p);
-            } else if (chi2 < p.chi2_max) {
+            if (chi2 < p.chi2_max) {
                 const float u = fmaf(-chi2, p.inv_chi2_max, 1.0f);
                 w = u * u;
             }
@@ -903,18 +906,26 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 load_track(A, a + c0 + lane, t);
             }
         };
-        // pass 1: per wavefront and candidate, the tracks passing the pre-cut
+        // pass 1: per wavefront and candidate, the tracks passing the pre-cut,
+        // and per track the sum of its terms of Eq. 18 (kept in the per-track
+        // key array, unused until the final pass)
         for (int c0 = r0; c0 < r1; c0 += 64) {
             const int i = c0 + lane;
             float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             chunk_tracks(c0, t);
             const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
+            float esum = 0.0f;
             for (int k = 0; k < nl; ++k) {
                 const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
-                const unsigned long long mm = __ballot(assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv);
+                const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
+                if (pass)
+                    esum += __expf(-0.5f * m.chi2);
+                const unsigned long long mm = __ballot(pass);
                 if (lane == 0)
                     S.wrun[wave][k] += __popcll(mm);
             }
+            if (i < r1)
+                S.u.f.BEST[i] = __float_as_uint(esum);
         }
         __syncthreads();
         // list lengths, starts and each wavefront's first slot per candidate
@@ -988,13 +999,10 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
             chunk_tracks(c0, t);
             const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
             float esum = 0.0f;
-            for (int k = 0; k < nl; ++k) {
-                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
-                if (assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv)
-                    esum += __expf(-0.5f * m.chi2);
-            }
-            if (i < r1)
+            if (i < r1) {
+                esum = __uint_as_float(S.u.f.BEST[i]);
                 S.u.f.BEST[i] = 0u;
+            }
             for (int k = 0; k < nl; ++k) {
                 const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
                 const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
@@ -1095,7 +1103,11 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                     const float rx = fmaf(dz, S.u.f.TX[sl], S.u.f.X[sl]) - dx;
                     const float ry = fmaf(dz, S.u.f.TY[sl], S.u.f.Y[sl]) - dy;
                     const float chi2 = S.u.f.WT[sl] * fmaf(rx, rx, ry * ry);
-                    c += (mv_weight(chi2, S.u.f.OTH[sl], p) >= p.w_count_mv) ? 1.0f : 0.0f;
+                    const float w = mv_weight(chi2, S.u.f.OTH[sl], p);
+                    c += (w >= p.w_count_mv) ? 1.0f : 0.0f;
+                    // the final pass reads the final weight and chi2 back
+                    S.u.f.OTH[sl] = w;
+                    S.u.f.X[sl] = chi2;
                 }
                 c = group_sum_rt(c, L);
                 if (has && gl == 0) {
