@@ -1040,14 +1040,15 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
     stamp<DEBUG>(ts, 5);
 
     // fit (Sec. 3.5): L lanes per vertex, L the largest power of two with
-    // L * vertices <= 64 for small teams (one wavefront fits them all and the
-    // others skip the fit: fewer instructions per event than spreading the
-    // vertices over the team, whose narrower groups need deeper sums, and
-    // the other teams on the CU use the freed issue slots), <= the team's
-    // lanes for large-event teams (one per CU: there latency decides)
+    // L * vertices <= 64 for small teams with at most 8 vertices (one
+    // wavefront fits them all and the others skip the fit: fewer instructions
+    // per event than spreading the vertices over the team, whose narrower
+    // groups need deeper sums, and the other teams on the CU use the freed
+    // issue slots), <= the team's lanes otherwise (many vertices, or one
+    // large-event team per CU, where latency decides)
     int lg = 6;
     {
-        const int target = ((!BIG && nl <= 64) ? 64 : NT) / max(nl, 1);
+        const int target = ((!BIG && nl <= 8) ? 64 : NT) / max(nl, 1);
         while (lg > 0 && (1 << lg) > target)
             --lg;
     }
@@ -1436,12 +1437,15 @@ static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStrea
     case 10256: return launch_pair<1, 256, MV, DEBUG>(A, st, ev);
     case 10512: return launch_pair<1, 512, MV, DEBUG>(A, st, ev);
     case 11024: return launch_pair<1, 1024, MV, DEBUG>(A, st, ev);
+    case 12048: return launch_pair<1, 2048, MV, DEBUG>(A, st, ev);
     case 20256: return launch_pair<2, 256, MV, DEBUG>(A, st, ev);
     case 20512: return launch_pair<2, 512, MV, DEBUG>(A, st, ev);
     case 21024: return launch_pair<2, 1024, MV, DEBUG>(A, st, ev);
+    case 22048: return launch_pair<2, 2048, MV, DEBUG>(A, st, ev);
     case 40256: return launch_pair<4, 256, MV, DEBUG>(A, st, ev);
     case 40512: return launch_pair<4, 512, MV, DEBUG>(A, st, ev);
     case 41024: return launch_pair<4, 1024, MV, DEBUG>(A, st, ev);
+    case 42048: return launch_pair<4, 2048, MV, DEBUG>(A, st, ev);
     default: return hipErrorInvalidValue;
     }
 }
