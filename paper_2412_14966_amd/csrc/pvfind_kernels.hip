@@ -832,6 +832,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 S.wrun[0][k] = S.base[k];
             __syncthreads();
         }
+        const int obits = (nl > 1) ? 32 - __clz(nl - 1) : 0;
         for (int c0 = r0; c0 < r1; c0 += 64) {
             const int i = c0 + lane;
             const bool valid = i < r1;
@@ -842,20 +843,23 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 t[q] = gnext[q];
             if (c0 + 64 + lane < r1)
                 load_track(A, a + c0 + 64 + lane, gnext);
-            unsigned long long rem = __ballot(own >= 0);
-            int slot = -1;
-            while (rem) {
-                const int leader = __ffsll((long long)rem) - 1;
-                const int ol = __shfl(own, leader);
-                const unsigned long long mm = __ballot(own == ol);
-                if (own == ol)
-                    slot = S.wrun[wave][ol] + __popcll(mm & lanemask_lt(lane));
-                __builtin_amdgcn_wave_barrier();
-                if (lane == leader)
-                    S.wrun[wave][ol] += __popcll(mm);
-                __builtin_amdgcn_wave_barrier();
-                rem &= ~mm;
+            // lanes with the same owner: one ballot per bit of the owner's
+            // index, so the cost grows with log2 of the vertex count, not
+            // with the number of owners present in the chunk
+            unsigned long long mm = __ballot(own >= 0);
+            for (int bit = 0; bit < obits; ++bit) {
+                const bool set = (own >> bit) & 1;
+                const unsigned long long bb = __ballot(set);
+                mm &= set ? bb : ~bb;
             }
+            int slot = -1;
+            const unsigned long long below = mm & lanemask_lt(lane);
+            if (own >= 0)
+                slot = S.wrun[wave][own] + __popcll(below);
+            __builtin_amdgcn_wave_barrier();
+            if (own >= 0 && below == 0ull)
+                S.wrun[wave][own] += __popcll(mm);
+            __builtin_amdgcn_wave_barrier();
             if (valid) {
                 const int g = a + i;
                 if (slot >= 0) {
