@@ -190,7 +190,7 @@ typedef struct {
 typedef struct {
     int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4 */
     int32_t track_capacity;            /* tracks per event held in LDS by small teams:
-                                          256, 512, 1024 or 2048; larger events go to
+                                          256, 512, 1024, 1536 or 2048; larger events go to
                                           a second launch with 4096-track teams       */
     int32_t persistent;                /* 2: one team per event, hardware-scheduled;
                                           4: as 2, teams launched in the order of a

@@ -82,8 +82,10 @@ int validate_schedule(const pv_schedule &s)
 {
     if (s.waves_per_team != 1 && s.waves_per_team != 2 && s.waves_per_team != 4)
         return fail(PV_EINVAL, "schedule: waves_per_team must be 1, 2 or 4 (got %d)", s.waves_per_team);
-    if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024 && s.track_capacity != 2048)
-        return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512, 1024 or 2048 (got %d)", s.track_capacity);
+    if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024 && s.track_capacity != 1536 &&
+        s.track_capacity != 2048)
+        return fail(PV_EINVAL, "schedule: track_capacity must be 256, 512, 1024, 1536 or 2048 (got %d)",
+                    s.track_capacity);
     if (s.persistent < 1 || s.persistent > 4)
         return fail(PV_EINVAL, "schedule: persistent must be 1, 2, 3 or 4 (got %d)", s.persistent);
     if (s.persistent == 1 || s.persistent == 3)
@@ -495,7 +497,7 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
     }
     int rc = PV_OK;
     bool have = false;
-    const int waves[3] = {1, 2, 4}, caps[4] = {256, 512, 1024, 2048}, modes[2] = {2, 4};
+    const int waves[3] = {1, 2, 4}, caps[5] = {256, 512, 1024, 1536, 2048}, modes[2] = {2, 4};
     for (int w : waves)
         for (int c : caps)
             for (int m : modes) {

@@ -1441,14 +1441,17 @@ static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStrea
     case 10256: return launch_pair<1, 256, MV, DEBUG>(A, st, ev);
     case 10512: return launch_pair<1, 512, MV, DEBUG>(A, st, ev);
     case 11024: return launch_pair<1, 1024, MV, DEBUG>(A, st, ev);
+    case 11536: return launch_pair<1, 1536, MV, DEBUG>(A, st, ev);
     case 12048: return launch_pair<1, 2048, MV, DEBUG>(A, st, ev);
     case 20256: return launch_pair<2, 256, MV, DEBUG>(A, st, ev);
     case 20512: return launch_pair<2, 512, MV, DEBUG>(A, st, ev);
     case 21024: return launch_pair<2, 1024, MV, DEBUG>(A, st, ev);
+    case 21536: return launch_pair<2, 1536, MV, DEBUG>(A, st, ev);
     case 22048: return launch_pair<2, 2048, MV, DEBUG>(A, st, ev);
     case 40256: return launch_pair<4, 256, MV, DEBUG>(A, st, ev);
     case 40512: return launch_pair<4, 512, MV, DEBUG>(A, st, ev);
     case 41024: return launch_pair<4, 1024, MV, DEBUG>(A, st, ev);
+    case 41536: return launch_pair<4, 1536, MV, DEBUG>(A, st, ev);
     case 42048: return launch_pair<4, 2048, MV, DEBUG>(A, st, ev);
     default: return hipErrorInvalidValue;
     }
