@@ -264,6 +264,16 @@ def test_config4_high_pileup_sample():
     check(b, debug=True, name="mu=40 800 events")
 
 
+@pytest.mark.parametrize("cap", [1536, 2048])
+def test_config4_high_pileup_large_teams(cap):
+    """High pile-up under the schedules that suit it: four-wavefront teams
+    holding 1536 or 2048 tracks; with 1536 the few larger events (about 1 %)
+    go to the large-event launch."""
+    b = synth.generate("pp_mu40_20kev", n_events=800, keep_truth=False)
+    check(b, schedule=dict(waves_per_team=4, track_capacity=cap, persistent=4, teams_per_cu=0), debug=True,
+          name=f"mu=40 800 events, capacity {cap}")
+
+
 def test_sorted_launch_over_several_ordering_chunks():
     """40,000 events: the ordering launch holds 16,384 events per pass, so the
     sorted schedule's order spans three passes; every event is compared."""
