@@ -122,6 +122,35 @@ def served_leg(pv, synth, n_events):
     return out
 
 
+def batched_leg(pv, synth, workload: str, steps: int, warmup: int) -> dict:
+    """Events/s of one further batched workload (beam-gas, high pile-up) under
+    the schedule pv_autotune picks for it: steps bracketed by HIP events on the
+    current stream, inputs resident in device memory."""
+    import torch
+    batch = synth.generate(workload, keep_truth=False)
+    params = pv.pv_params_default()
+    db = pv.to_device(batch)
+    out = pv.alloc_outputs(db, params.max_vertices_per_event)
+    best, _ = pv.pv_autotune(db, out, params, reps=3)
+    sched = pv.pv_schedule(best["waves_per_team"], best["track_capacity"], best["persistent"], best["teams_per_cu"])
+    for _ in range(warmup):
+        pv.pv_find_sched(db, out, params, sched)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        pv.pv_find_sched(db, out, params, sched)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    res = {"events": batch.n_events, "tracks": batch.n_tracks, "events_per_s": round(batch.n_events / (ms / 1e3), 1),
+           "ms_per_step": round(ms, 5), "n_vertices": int(out.n_vertices.sum().item()), "schedule": best}
+    log(f"{workload}: {res['events_per_s']:.4g} events/s under {best}")
+    del db, out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +167,9 @@ def main():
                     help="run one device-to-device copy of this size first (HBM counter calibration)")
     ap.add_argument("--served-events", type=int, default=20000,
                     help="events of the served mix replayed per offered rate (0 skips the served leg)")
+    ap.add_argument("--batched-configs", default="pp_mu5_gas_50kev,pp_mu40_20kev",
+                    help="further batched workloads timed last, each under its own autotuned schedule "
+                         "(empty skips them)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -219,6 +251,17 @@ def main():
     main_us = main_ms / ncalls * 1e3
     large_us = large_ms / ncalls * 1e3
     log(f"main fused kernel {main_us:.1f} us, large-event kernel {large_us:.1f} us per step")
+
+    # spread of single steps: one event pair around each of K more steps
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    marks[0].record(stream)
+    for k in range(args.steps):
+        step()
+        marks[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = np.array([marks[k].elapsed_time(marks[k + 1]) * 1e3 for k in range(args.steps)])
+    step_us = {"median": round(float(np.median(per_step)), 2), "p10": round(float(np.percentile(per_step, 10)), 2),
+               "p90": round(float(np.percentile(per_step, 90)), 2)}
 
     nv = int(out.n_vertices.sum().item())
     abytes = algorithmic_bytes(batch.n_tracks, batch.n_events, nv)
@@ -318,14 +361,19 @@ def main():
     if args.served_events > 0:
         served = served_leg(pv, synth, args.served_events)
 
+    # last, because each autotune run changes the library's default schedule
+    batched_configs = {}
+    for wl in (w for w in args.batched_configs.split(",") if w):
+        batched_configs[wl] = batched_leg(pv, synth, wl, args.steps, args.warmup)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
                    "n_vertices": nv, "schedule": schedule},
-        "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event, "multivertex": multivertex,
-        "served": served,
+        "step_us": step_us, "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event,
+        "multivertex": multivertex, "served": served, "batched_configs": batched_configs,
     }
     print(json.dumps(line), flush=True)
 
