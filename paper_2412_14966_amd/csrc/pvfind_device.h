@@ -39,16 +39,17 @@ __device__ __forceinline__ int wave_min(int v)
     return v;
 }
 
-// Sum over aligned groups of L lanes; every lane of a group gets the same
-// bits (the pairs added are the same, addition is commutative).  Within a
-// row of 16 lanes the partners come from DPP (quad permutes, half-row and
-// row mirrors), across rows from a swizzle and a permute.
+// Group sums below: every lane of a group gets the same bits (the pairs
+// added are the same, addition is commutative).  Within a row of 16 lanes the
+// partners come from DPP (quad permutes, half-row and row mirrors), across
+// rows from a swizzle and a permute.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
+// Sum over aligned groups of L lanes, for a compile-time L.
 template <int L>
 __device__ __forceinline__ float group_sum(float v)
 {
@@ -67,9 +68,9 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-// group_sum<L> for a wavefront-uniform L (one copy of the caller's code
-// serves every group size).  Every butterfly level runs and a select keeps
-// the levels below L, so no branch depends on L.
+// Sum over aligned groups of L lanes, for a wavefront-uniform L (one copy of
+// the caller's code serves every group size).  Every butterfly level runs and
+// a select keeps the levels below L, so no branch depends on L.
 __device__ __forceinline__ float group_sum_rt(float v, int L)
 {
     float t = dpp_f<0xB1>(v);
@@ -85,6 +86,52 @@ __device__ __forceinline__ float group_sum_rt(float v, int L)
     t = __shfl_xor(v, 32);
     v = (L >= 64) ? v + t : v;
     return v;
+}
+
+// The N sums of one Newton step for groups whose size L = 2^lg varies from
+// lane to lane: the groups are aligned blocks, so every butterfly partner of a
+// lane lies in its own group.  The levels run up to lgmax, the wavefront's
+// largest group (one scalar branch per level), each kept by a select where
+// the lane's group is smaller.
+template <int N>
+__device__ __forceinline__ void group_sum_n_var_rt(float v[N], int L, int lgmax)
+{
+    if (lgmax >= 1)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = dpp_f<0xB1>(v[q]);
+            v[q] = (L >= 2) ? v[q] + t : v[q];
+        }
+    if (lgmax >= 2)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = dpp_f<0x4E>(v[q]);
+            v[q] = (L >= 4) ? v[q] + t : v[q];
+        }
+    if (lgmax >= 3)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = dpp_f<0x141>(v[q]);
+            v[q] = (L >= 8) ? v[q] + t : v[q];
+        }
+    if (lgmax >= 4)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = dpp_f<0x140>(v[q]);
+            v[q] = (L >= 16) ? v[q] + t : v[q];
+        }
+    if (lgmax >= 5)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v[q]), 0x401F));
+            v[q] = (L >= 32) ? v[q] + t : v[q];
+        }
+    if (lgmax >= 6)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const float t = __shfl_xor(v[q], 32);
+            v[q] = (L >= 64) ? v[q] + t : v[q];
+        }
 }
 
 // The N sums of one Newton step at once, for a wavefront-uniform group of

@@ -94,6 +94,7 @@ struct __align__(16) Smem {
             short ps[64], pe[64];   // peak search: pending proto-clusters
             int po[64];             // their LDS offsets
         };
+        short lmap[64 * W];  // fit: per lane, its vertex | log2 of its group's lanes << 8, -1 for none
     };
     int vout[V];
     int ntk[MV ? V : 1];     // multi-vertex: tracks of final weight >= w_count_mv
@@ -260,15 +261,18 @@ __device__ __forceinline__ void peak_search(Smem<W, CAP, BIG, MV> &S, const KPar
 // L = 1 << lg lanes per vertex, wavefront-uniform (scalar): one copy of the
 // code serves every group size.
 template <int W, int CAP, bool BIG, bool MV>
-__device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KParams &p, int nl, int L, int lg)
+__device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KParams &p, int nl, int lg, bool prop)
 {
-    constexpr int NT = 64 * W;
-    const int G = NT >> lg;
     const int tid = threadIdx.x;
-    const int gid = tid >> lg, gl = tid & (L - 1);
-    for (int k0 = 0; k0 < nl; k0 += G) {
-        const int k = k0 + gid;
-        const bool has = k < nl;
+    // uniform: L = 2^lg lanes per vertex; proportional: the lane map's groups
+    const int m = prop ? (int)S.lmap[tid] : (((tid >> lg) < nl) ? ((tid >> lg) | (lg << 8)) : -1);
+    const bool has = m >= 0;
+    const int k = has ? (m & 0xFF) : 0;
+    const int L = prop ? (1 << (has ? (m >> 8) : 0)) : (1 << lg);
+    const int gl = tid & (L - 1);
+    // the deepest butterfly level any group of this wavefront needs
+    const int lgmax = prop ? __builtin_amdgcn_readfirstlane(-wave_min(-(has ? (m >> 8) : 0))) : lg;
+    {
         const int beg = has ? S.base[k] : 0, ck = has ? S.cnt[k] : 0;
         float rX[kRegTracks], rY[kRegTracks], rTX[kRegTracks], rTY[kRegTracks], rW[kRegTracks];
         float rO[MV ? kRegTracks : 1];
@@ -321,7 +325,10 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
                 }
             }
             float r[7] = {a.s0, a.sx, a.sy, a.szz, a.gx, a.gy, a.gz};
-            group_sum_n_rt<7>(r, lg);
+            if (prop)
+                group_sum_n_var_rt<7>(r, L, lgmax);
+            else
+                group_sum_n_rt<7>(r, lg);
             const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6];
             if (active) {
                 // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
@@ -1058,7 +1065,70 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
     }
     lg = __builtin_amdgcn_readfirstlane(lg);   // the same on every lane: keep it scalar
     const int L = 1 << lg;
-    fit_vertices<W, CAP, BIG, MV>(S, p, nl, L, lg);
+    // Fits spread over the team (more than 8 vertices) give vertex k 2^lk
+    // lanes, about in proportion to its tracks (a wavefront iterates until its
+    // slowest vertex converges, so with equal groups the largest vertex would
+    // set the pace): lk = floor(log2(c_k B / C)) for the team's B lanes and C
+    // tracks in all, then the vertex with the most tracks per lane doubles its
+    // lanes while the budget allows.  The blocks are placed largest first, so
+    // each is aligned to its size, as the group sums need.  Fewer vertices,
+    // where the balancing costs more than it saves, and more than 64 keep L
+    // lanes each.
+    const bool prop = nl > 8 && nl <= 64;
+    if (prop && wave == 0) {
+        const int budget = NT;
+        int lk = lg, off = lane << lg, used = 0;
+        bool fits = false;
+        {
+            const int c = (lane < nl) ? S.cnt[lane] : 0;
+            const int C = __shfl(wave_incl_scan(c, lane), 63);
+            if (C > 0) {
+                const int q = (lane < nl) ? max(1, (c * budget) / C) : 1;
+                int lp = min(6, 31 - __clz(q));
+                int tot = __shfl(wave_incl_scan((lane < nl) ? (1 << lp) : 0, lane), 63);
+                if (tot <= budget) {
+                    fits = true;
+                    for (int it = 0; it < 64; ++it) {
+                        // worst tracks per lane, lowest index on ties
+                        const int r = (lane < nl) ? ((c + (1 << lp) - 1) >> lp) : 0;
+                        const int key = -wave_min(-((r << 8) | (255 - lane)));
+                        const int kb = 255 - (key & 0xFF);
+                        const int lb = __shfl(lp, kb);
+                        if ((key >> 8) <= 1 || lb >= 6 || tot + (1 << lb) > budget)
+                            break;
+                        if (lane == kb)
+                            ++lp;
+                        tot += 1 << lb;
+                    }
+                    lk = lp;
+                    used = tot;
+                    int run = 0;
+                    for (int cl = 6; cl >= 0; --cl) {
+                        const bool mine = lane < nl && lk == cl;
+                        const unsigned long long mm = __ballot(mine);
+                        if (mine)
+                            off = run + (__popcll(mm & lanemask_lt(lane)) << cl);
+                        run += __popcll(mm) << cl;
+                    }
+                }
+            }
+        }
+        if (fits) {
+            for (int t = used + lane; t < NT; t += 64)
+                S.lmap[t] = -1;
+            if (lane < nl)
+                for (int u = 0; u < (1 << lk); ++u)
+                    S.lmap[off + u] = (short)(lane | (lk << 8));
+        } else {
+            for (int t = lane; t < NT; t += 64) {
+                const int kk = t >> lg;
+                S.lmap[t] = (kk < nl) ? (short)(kk | (lg << 8)) : (short)-1;
+            }
+        }
+    }
+    if (prop)
+        __syncthreads();
+    fit_vertices<W, CAP, BIG, MV>(S, p, nl, lg, prop);
     __syncthreads();
     stamp<DEBUG>(ts, 6);
 
