@@ -16,22 +16,28 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pv_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PV_ORACLE_LIB names another build of the oracle (the mutation test loads
+# planted-mistake builds this way); it is loaded as it is, never rebuilt
+_LIB_OVERRIDE = os.environ.get("PV_ORACLE_LIB")
+_LIB = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle.so")
 
 TR_HIST, TR_ASSOC, TR_NONFINITE = 1, 2, 4
 EV_NONFINITE_INPUT, EV_TOO_MANY_TRACKS, EV_VERTEX_OVERFLOW, EV_OFFSETS_INVALID = 1, 2, 4, 8
 VX_NOT_CONVERGED = 1
 
 
-def build(force: bool = True) -> str:
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
+             "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True, src: str = _SRC, out: Optional[str] = None) -> str:
     """Compile liboracle.so with gcc (binary32 stage needs -ffp-contract=off)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
-               "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+    out = out or os.path.join(_HERE, "liboracle.so")
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-I", _HERE, "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class OrcParams(ctypes.Structure):
@@ -49,14 +55,15 @@ class OrcParams(ctypes.Structure):
         ("max_tracks", ctypes.c_int), ("max_vertices", ctypes.c_int),
         ("assoc_mode", ctypes.c_int), ("chi2_max_mv", ctypes.c_double), ("chi2_window_mv", ctypes.c_double),
         ("conv_dz_mv", ctypes.c_double), ("dup_ratio", ctypes.c_double), ("w_count_mv", ctypes.c_double),
-        ("peak_mode", ctypes.c_int),
+        ("peak_mode", ctypes.c_int), ("tie_rel", ctypes.c_double), ("iter_override_bin", ctypes.c_int),
+        ("iter_override_n", ctypes.c_int),
     ]
 
 
 class OrcCluster(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int), ("hi", ctypes.c_int), ("peak", ctypes.c_int), ("z_seed", ctypes.c_double),
                 ("kept", ctypes.c_int), ("n_assoc", ctypes.c_int), ("own_lo", ctypes.c_int),
-                ("own_hi", ctypes.c_int)]
+                ("own_hi", ctypes.c_int), ("n_near_cut", ctypes.c_int)]
 
 
 class OrcVertex(ctypes.Structure):
@@ -74,7 +81,8 @@ _VERTEX_DTYPE = np.dtype([("x", "f8"), ("y", "f8"), ("z", "f8"), ("cov", "f8", (
                           ("bin_lo", "i4"), ("bin_hi", "i4"), ("peak_bin", "i4"), ("n_iter", "i4"),
                           ("flags", "i4"), ("n_near", "i4"), ("dup_margin", "f8")], align=True)
 _CLUSTER_DTYPE = np.dtype([("lo", "i4"), ("hi", "i4"), ("peak", "i4"), ("z_seed", "f8"), ("kept", "i4"),
-                           ("n_assoc", "i4"), ("own_lo", "i4"), ("own_hi", "i4")], align=True)
+                           ("n_assoc", "i4"), ("own_lo", "i4"), ("own_hi", "i4"), ("n_near_cut", "i4")],
+                          align=True)
 assert _VERTEX_DTYPE.itemsize == ctypes.sizeof(OrcVertex)
 assert _CLUSTER_DTYPE.itemsize == ctypes.sizeof(OrcCluster)
 
@@ -84,7 +92,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_OVERRIDE and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER
@@ -287,6 +295,7 @@ class OracleResult:
     zpoca: Optional[np.ndarray] = None
     sigma: Optional[np.ndarray] = None
     bin: Optional[np.ndarray] = None
+    params: Optional[Dict] = None   # the parameter overrides this result was computed with
 
 
 def find(batch, params=None, debug: bool = False, n_threads: int = 0) -> OracleResult:
@@ -319,7 +328,7 @@ def find(batch, params=None, debug: bool = False, n_threads: int = 0) -> OracleR
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     res = OracleResult(n_vertices=nv[:ne], status=st[:ne], vertices=vtx[:ne * maxv].reshape(ne, maxv),
-                       track_vertex=tv[:nt], track_weight=tw[:nt])
+                       track_vertex=tv[:nt], track_weight=tw[:nt], params=dict(params or {}))
     if debug:
         res.hist = hist[:ne * nb].reshape(ne, nb)
         res.clusters = cls[:ne * maxv].reshape(ne, maxv)

@@ -81,6 +81,9 @@ void orc_params_default(orc_params *p)
     p->dup_ratio = 25.0;
     p->w_count_mv = 0.5;
     p->peak_mode = ORC_PEAK_Z_ORDERED;
+    p->tie_rel = 1e-5;
+    p->iter_override_bin = -1;
+    p->iter_override_n = 0;
 }
 
 int orc_nbins(const orc_params *p)
@@ -585,7 +588,7 @@ static double fit_weight(double chi2, const double *others, int k, const orc_par
 /* others == NULL: Tukey weights and the x86 criterion; otherwise the weights
    of Eq. 18 and the GPU criterion */
 static int fit_core(const float *const trk[8], const int *idx, const double *others, int n,
-                    double x_seed, double y_seed, double z_seed, const orc_params *p,
+                    double x_seed, double y_seed, double z_seed, const orc_params *p, int force_iter,
                     orc_vertex *v, double *w_out)
 {
     double alpha[3] = {x_seed, y_seed, z_seed};
@@ -605,7 +608,8 @@ static int fit_core(const float *const trk[8], const int *idx, const double *oth
         Wd[k] = (Vx > 0.0 && isfinite(Vx)) ? 1.0 / Vx : 0.0;   /* 0 marks an unusable track */
     }
 
-    for (it = 1; it <= p->max_iter; ++it) {
+    const int n_max = force_iter > 0 ? force_iter : p->max_iter;
+    for (it = 1; it <= n_max; ++it) {
         double grad[3] = {0, 0, 0}, hess[3][3], sumw = 0.0;
         memset(hess, 0, sizeof(hess));
         for (k = 0; k < n; ++k) {
@@ -660,10 +664,9 @@ static int fit_core(const float *const trk[8], const int *idx, const double *oth
         if (frag < margin)
             margin = frag;
 
-        if (below1 && below2) {
-            converged = 1;
+        converged = below1 && below2;
+        if (converged && force_iter <= 0)
             break;
-        }
     }
 
     if (failed || n_iter == 0) {
@@ -727,14 +730,14 @@ int orc_fit(const float *const trk[8], const int *idx, int n,
             double x_seed, double y_seed, double z_seed, const orc_params *p,
             orc_vertex *v, double *w_out)
 {
-    return fit_core(trk, idx, NULL, n, x_seed, y_seed, z_seed, p, v, w_out);
+    return fit_core(trk, idx, NULL, n, x_seed, y_seed, z_seed, p, 0, v, w_out);
 }
 
 int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, int n,
                double x_seed, double y_seed, double z_seed, const orc_params *p,
                orc_vertex *v, double *w_out)
 {
-    return fit_core(trk, idx, others, n, x_seed, y_seed, z_seed, p, v, w_out);
+    return fit_core(trk, idx, others, n, x_seed, y_seed, z_seed, p, 0, v, w_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -743,8 +746,8 @@ int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, 
 /*
  * Every associable track is weighted to every candidate.  Candidate j fits
  * the tracks whose chi2 at its seed is below chi2_window_mv (the pre-cut of
- * Sec. 5, in binary32 as below; the lists of all candidates together hold at
- * most max_tracks entries, else the event is flagged as too large), with
+ * Sec. 5, as below; the lists of all candidates together hold at most
+ * max_tracks entries, else the event is flagged as too large), with
  * W_ij = 1 / Vx at its seed as in the partition fit, and the
  * weights of Eq. 18, in which the other candidates enter at their seeds
  * (their terms exp(-chi2_ik / 2) are summed over the candidates whose
@@ -760,46 +763,33 @@ int orc_fit_mv(const float *const trk[8], const int *idx, const double *others, 
  * the largest final weight (the earlier one on ties), or (-1, 0).
  */
 /*
- * The pre-cut decides which tracks enter a fit, an integer decision, so it is
- * defined in binary32 with the operations written out (as the projection):
- * frame at the beamline point of the candidate's peak-bin centre
- * z_i = z_min + (i + 1/2) dz, seed offset d0 = delta dz (Eq. 4-5, delta from
- * the bin contents converted to binary32), track position at z_i relative to
- * that point, V_x of Eq. 2 at the seed, residual at the seed (Eq. 9) and
- * chi2 = W (rx^2 + ry^2) (Eq. 7); fmaf is the fused multiply-add.  The chi2
- * is also the one whose exp(-chi2 / 2) enters Eq. 18 for the other
- * candidates.  Returns W (0: unusable track) and the chi2.
+ * Pre-cut (Sec. 5, GPU variant): candidate j fits only the tracks within a
+ * chi2 window of its seed.  The chi2 is that of Eq. 7 with the residual of
+ * Eq. 9 taken at the seed position alpha_j = (x_b + t_x,b z_seed,
+ * y_b + t_y,b z_seed, z_seed) (Sec. 3.3: the seed lies on the beamline) and
+ * W = 1 / V_x with V_x from Eq. 2 at the seed, as the fit itself starts
+ * (Sec. 3.5), all in binary64.  Returns W (0: unusable track) and the chi2.
+ * The same chi2 gives the terms exp(-chi2 / 2) by which candidate j enters
+ * the other candidates' weights in Eq. 18.
  */
-static float mv_seed_offset(const int *h, int nb, int i, const orc_params *p)
+static double mv_seed_chi2(const float *const ev[8], int i, const double seed[3], double *W)
 {
-    const int Ni = h[i];
-    const int Nm = (i > 0) ? h[i - 1] : 0;
-    const int Np = (i + 1 < nb) ? h[i + 1] : 0;
-    const int den = 2 * Ni - Np - Nm;
-    float delta = (den > 0) ? (0.5f * (float)(Np - Nm)) / (float)den : 0.0f;
-    if (delta < -0.5f)
-        delta = -0.5f;
-    if (delta > 0.5f)
-        delta = 0.5f;
-    return delta * p->dz;
+    const double x = ev[0][i], y = ev[1][i], z = ev[2][i], tx = ev[3][i], ty = ev[4][i];
+    const double dz = seed[2] - z;
+    const double Vx = (double)ev[5][i] + 2.0 * dz * (double)ev[6][i] + dz * dz * (double)ev[7][i];
+    *W = (Vx > 0.0 && isfinite(Vx)) ? 1.0 / Vx : 0.0;
+    const double rx = x + dz * tx - seed[0];
+    const double ry = y + dz * ty - seed[1];
+    return *W * (rx * rx + ry * ry);
 }
 
-static float mv_precut_chi2(const float *const ev[8], int i, const float beam[4], float zr, float d0, float *W)
+static int forced_iters(const orc_params *p, int peak)
 {
-    const float x = ev[0][i], y = ev[1][i], z = ev[2][i], tx = ev[3][i], ty = ev[4][i];
-    const float dzr = zr - z;
-    const float X = fmaf(dzr, tx, x) - (beam[0] + beam[2] * zr);
-    const float Y = fmaf(dzr, ty, y) - (beam[1] + beam[3] * zr);
-    const float dzs = dzr + d0;
-    const float V = fmaf(dzs, fmaf(dzs, ev[7][i], 2.0f * ev[6][i]), ev[5][i]);
-    *W = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
-    const float rx = fmaf(d0, tx, X) - beam[2] * d0;
-    const float ry = fmaf(d0, ty, Y) - beam[3] * d0;
-    return *W * fmaf(rx, rx, ry * ry);
+    return (p->iter_override_bin >= 0 && peak == p->iter_override_bin) ? p->iter_override_n : 0;
 }
 
 static void mv_event(const float *const ev[8], int n, const float beam[4], const orc_params *p, const int *fl,
-                     const int *h, int nb, orc_cluster *cl, int ncl, int a, int *status, int *n_vtx,
+                     orc_cluster *cl, int ncl, int a, int *status, int *n_vtx,
                      orc_vertex *vtx, int *trk_vtx, double *trk_w)
 {
     const int gas_bin = orc_gas_bin(p);
@@ -818,22 +808,27 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
     /* pre-cut and the terms of Eq. 18 at the seeds */
     long total = 0;
     for (j = 0; j < ncl; ++j) {
-        const float zr = p->z_min + ((float)cl[j].peak + 0.5f) * p->dz;
-        const float d0 = mv_seed_offset(h, nb, cl[j].peak, p);
-        int m = 0;
+        const double zs = cl[j].z_seed;
+        const double seed[3] = {(double)beam[0] + (double)beam[2] * zs, (double)beam[1] + (double)beam[3] * zs, zs};
+        int m = 0, near = 0;
         for (i = 0; i < n; ++i) {
             if (!(fl[i] & ORC_TR_ASSOC))
                 continue;
-            float W;
-            const float chi2 = mv_precut_chi2(ev, i, beam, zr, d0, &W);
-            if (W > 0.0f && (double)chi2 < p->chi2_window_mv) {
+            double W;
+            const double chi2 = mv_seed_chi2(ev, i, seed, &W);
+            if (!(W > 0.0))
+                continue;
+            if (chi2 < p->chi2_window_mv) {
                 in[(size_t)j * nn + i] = 1;
-                e0[(size_t)j * nn + i] = exp(-0.5 * (double)chi2);
+                e0[(size_t)j * nn + i] = exp(-0.5 * chi2);
                 ++m;
             }
+            if (fabs(chi2 - p->chi2_window_mv) <= p->tie_rel * p->chi2_window_mv)
+                ++near;
         }
         cl[j].kept = 1;
         cl[j].n_assoc = m;
+        cl[j].n_near_cut = near;
         cl[j].own_lo = cl[j].own_hi = -1;
         total += m;
     }
@@ -860,7 +855,7 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
         const double zs = cl[j].z_seed;
         const double xs = (double)beam[0] + (double)beam[2] * zs;
         const double ys = (double)beam[1] + (double)beam[3] * zs;
-        ok[j] = !orc_fit_mv(ev, idx, oth, m, xs, ys, zs, p, &cand[j], w);
+        ok[j] = !fit_core(ev, idx, oth, m, xs, ys, zs, p, forced_iters(p, cl[j].peak), &cand[j], w);
         int cnt = 0, near = 0;
         for (k = 0; k < m; ++k) {
             wall[(size_t)j * nn + idx[k]] = w[k];
@@ -1018,7 +1013,7 @@ static void find_event(const float *const trk[8], int a, int n, const float beam
     if (overflow)
         *status |= ORC_EV_VERTEX_OVERFLOW;
     if (p->assoc_mode == ORC_ASSOC_MULTIVERTEX) {
-        mv_event(ev, n, beam, p, fl, h, nb, cl, ncl, a, status, n_vtx, vtx, trk_vtx, trk_w);
+        mv_event(ev, n, beam, p, fl, cl, ncl, a, status, n_vtx, vtx, trk_vtx, trk_w);
         if (clusters) {
             memcpy(clusters, cl, sizeof(orc_cluster) * (size_t)ncl);
             *n_clusters = ncl;
@@ -1049,7 +1044,7 @@ static void find_event(const float *const trk[8], int a, int n, const float beam
         const double xs = (double)beam[0] + (double)beam[2] * zs;
         const double ys = (double)beam[1] + (double)beam[3] * zs;
         orc_vertex v;
-        const int bad = orc_fit(ev, idx, m, xs, ys, zs, p, &v, w);
+        const int bad = fit_core(ev, idx, NULL, m, xs, ys, zs, p, forced_iters(p, cl[q].peak), &v, w);
         const int gas = cl[q].peak < gas_bin;
         int keep = !bad && cl[q].n_assoc >= (gas ? p->pv_min_gas : p->pv_min_pp);
         if (keep && !gas) {

@@ -69,6 +69,15 @@ typedef struct {
     /* splitting of proto-clusters (Sec. 3.3) */
     int    peak_mode;         /* 0: minima in z order (GPU variant); 1: the smallest minimum
                                  between the two largest maxima, recursively (x86 variant) */
+    /* reporting only (no effect on the results): a threshold decision whose
+       deciding quantity lies within tie_rel (relative) of its threshold is
+       counted as one that an evaluation in another precision may take the
+       other way */
+    double tie_rel;
+    /* test hook: the fit of the cluster whose highest bin is
+       iter_override_bin runs exactly iter_override_n iterations (stopping
+       early only if it fails); -1 / 0 leave every fit alone */
+    int    iter_override_bin, iter_override_n;
 } orc_params;
 
 #define ORC_PEAK_Z_ORDERED 0
@@ -83,6 +92,8 @@ typedef struct {
     int kept;                  /* survives the association step            */
     int n_assoc;               /* tracks owned after the association step  */
     int own_lo, own_hi;        /* bins owned after the association step    */
+    int n_near_cut;            /* multi-vertex: associable tracks whose chi2 at
+                                  the seed lies within tie_rel of the pre-cut */
 } orc_cluster;
 
 typedef struct {

@@ -181,6 +181,28 @@ def test_cubic_kernel_golden_codes_and_masses():
     assert c[2400] == 1 and c.sum() == 1
 
 
+def test_cubic_kernel_binary32_rounding():
+    """The oracle emulates binary32 by rounding each binary64 operation once;
+    on non-dyadic inputs its edge codes must equal numpy's native binary32
+    arithmetic of the same operations (one reciprocal per track, then a
+    product per edge), which a missed rounding step would not."""
+    rng = np.random.default_rng(77)
+    f = np.float32
+    n_checked = 0
+    for _ in range(2000):
+        zp = f(rng.uniform(-600, 400))
+        sw = f(rng.uniform(0.02, 3.2))
+        e = f(zp + f(rng.uniform(-1.0, 1.0)) * sw)   # an arbitrary edge inside the window
+        r = f(1.0) / sw
+        s = f(f(e - zp) * r)
+        s = min(max(s, f(-1.0)), f(1.0))
+        P = f(f(0.5) + f(s * f(f(0.75) - f(f(0.25) * f(s * s)))))
+        want = int(np.rint(np.float64(P) * 65536.0))
+        assert oracle.edge_code(float(e), float(zp), float(sw)) == want
+        n_checked += 0 < want < 65536
+    assert n_checked > 1500
+
+
 def test_cubic_kernel_approximates_gaussian_cdf():
     """The kernel stands in for the Gaussian bin integral (Sec. 3.2): its
     cumulative stays within 0.021 of Phi((e - z_poca)/sigma) everywhere, and
@@ -747,6 +769,13 @@ def test_final_selection_beamline_distance_and_regions():
     assert nv((0.35, 0.0, -400.0)) == 1
     # tilted beamline: the distance is measured to the beamline at the vertex z
     assert nv((0.35, 0.0, 100.0), beam=(0.0, 0.0, 0.0035, 0.0)) == 1
+    # Table 2: at least 4 tracks in a pp vertex, 3 in a beam-gas vertex
+    # (after the association step's own 3 / 2, Sec. 3.4)
+    for P, n, want in (((0.0, 0.0, 10.0), 3, 0), ((0.0, 0.0, 10.0), 4, 1),
+                       ((0.0, 0.0, -400.0), 2, 0), ((0.0, 0.0, -400.0), 3, 1)):
+        r = oracle.find(synth.from_tracks([rows_through(P, n)]), debug=True)
+        assert r.n_clusters[0] == 1 and r.clusters[0, 0]["kept"] == 1 and r.clusters[0, 0]["n_assoc"] == n
+        assert r.n_vertices[0] == want, (P, n)
 
 
 def test_fit_singular_when_one_track_keeps_weight():
@@ -909,6 +938,52 @@ def test_mv_precut_bounds_the_candidate_track_lists():
         assert np.all(cl["n_assoc"] == n_assoc)
 
 
+def test_mv_precut_is_the_chi2_at_the_seed():
+    """Sec. 5 pre-cut with Eq. 7 and Eq. 9 at the seed and Eq. 2 at the seed.
+    Probe tracks with sigma_poca above the 1.5 mm histogram cut leave the
+    histogram (hence the seed) alone but are associable.  Each probe passes
+    at a chosen transverse distance d from the seed point on a tilted,
+    displaced beamline, 10 mm downstream of its state, with slope covariance
+    terms, so that V_x = Vxx + 2*10*Vxtx + 100*Vtxtx = 0.42; it must enter the
+    candidate exactly when d^2 / V_x < 25.  The probes sit at 25 (1 -+ 2e-3):
+    a chi2 taken at the bin centre instead of the seed, without the beamline
+    tilt, with V_x = Vxx, or with a sign or factor of Eq. 2 wrong moves them
+    across the cut."""
+    beam = (0.5, -0.25, 1e-3, -2e-3)
+    rng = np.random.default_rng(51)
+    z0 = 40.0 + 0.2 * 0.25 + 0.03          # off the bin centre: a seed offset delta dz != 0
+    P = (beam[0] + beam[2] * z0, beam[1] + beam[3] * z0, z0)
+    core = _exact_tracks_through(P, 30, rng)
+    prm = {"assoc_mode": 1, "pv_min_pp": 0, "max_rho_pp": 1e9}
+    r0 = oracle.find(synth.from_tracks([core], beamline=beam), prm, debug=True)
+    assert r0.n_clusters[0] == 1
+    cl0 = r0.clusters[0, 0]
+    zs = float(cl0["z_seed"])
+    zc = -600.0 + (int(cl0["peak"]) + 0.5) * 0.25
+    assert abs(zs - zc) > 0.02                                     # the seed is off the bin centre
+    seed = (beam[0] + beam[2] * zs, beam[1] + beam[3] * zs, zs)
+    vxx, vxtx, vtxtx, t, L = 0.25, 0.004, 0.0009, 0.3, 10.0
+    Vx = vxx + 2 * L * vxtx + L * L * vtxtx
+    probes, inside = [], 0
+    for k, ang in enumerate(np.linspace(0.0, 2 * np.pi, 12, endpoint=False)):
+        f = 1 - 2e-3 if k % 2 == 0 else 1 + 2e-3
+        d = math.sqrt(25.0 * Vx * f)
+        tx, ty = t * math.cos(ang + 0.4), t * math.sin(ang + 0.4)
+        # the track passes (seed + d (cos, sin)) at z_seed; its state is L upstream
+        x = seed[0] + d * math.cos(ang) - tx * L
+        y = seed[1] + d * math.sin(ang) - ty * L
+        probes.append([x, y, zs - L, tx, ty, vxx, vxtx, vtxtx])
+        inside += f < 1
+    ev = np.concatenate([core, np.array(probes)])
+    r = oracle.find(synth.from_tracks([ev], beamline=beam), prm, debug=True)
+    assert np.array_equal(r.hist, r0.hist)                         # the probes stay out of the histogram
+    assert np.all(r.bin[30:] >= 0)                                 # ... but are associable
+    cl = r.clusters[0, 0]
+    assert cl["z_seed"] == zs
+    assert cl["n_assoc"] == 30 + inside == 36
+    assert cl["n_near_cut"] == 0
+
+
 def test_mv_duplicate_rejection_is_the_greedy_rule():
     """Brute force on the candidates: with the selection opened up and no
     duplicate test, every successful fit is written; with the test, the kept
@@ -966,10 +1041,10 @@ def test_mv_track_reports_its_largest_weight():
             rx = tr[None, :, 0] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 3] - x[:, None]
             ry = tr[None, :, 1] + (z[:, None] - tr[None, :, 2]) * tr[None, :, 4] - y[:, None]
             return W * (rx * rx + ry * ry)
-        # the oracle takes the pre-cut in binary32 (an integer decision): here in
-        # binary64, so pairs within 1e-4 of the cut are left undecided
+        # both sides take the pre-cut in binary64, in another order of
+        # operations: pairs within 1e-12 of the cut are left undecided
         c0 = chi2_at(np.zeros(nv), np.zeros(nv), zs)       # the batches' beamline is at x = y = 0
-        amb = np.abs(c0 - p["chi2_window_mv"]) < 1e-4 * p["chi2_window_mv"]
+        amb = np.abs(c0 - p["chi2_window_mv"]) < 1e-12 * p["chi2_window_mv"]
         if np.any(amb & (W > 0) & ok[None, :]):
             continue
         events += 1

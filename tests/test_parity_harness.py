@@ -1,0 +1,84 @@
+"""The parity harness (tests/parity.py) on the CPU, with a stand-in for the
+GPU result built from the oracle itself: its tie rules accept exactly the
+differences they are meant to accept and reject the rest."""
+import copy
+
+import numpy as np
+
+import oracle
+import parity
+from paper_2412_14966_amd import synth
+
+
+def _result(batch, prm, debug=True):
+    return oracle.find(batch, prm, debug=debug)
+
+
+def _first_vertex(o):
+    e = int(np.nonzero(o.n_vertices > 0)[0][0])
+    return e, 0
+
+
+def test_identical_results_pass():
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    o = _result(b, {})
+    rep = parity.compare(b, copy.deepcopy(o), o, debug=True)
+    assert rep.ok(), rep.problems
+    assert rep.ties == 0
+
+
+def test_iteration_tie_is_refitted_at_the_gpu_iteration_count():
+    """A vertex that stops one iteration later on the 'GPU' side: with a small
+    oracle margin it is refitted at that count and matches; with a large one it
+    is a failure; a refit that does not match the stand-in's position fails."""
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    o = _result(b, {})
+    e, k = _first_vertex(o)
+    peak, n_it = int(o.vertices[e, k]["peak_bin"]), int(o.vertices[e, k]["n_iter"])
+    forced = oracle.find(b, {"iter_override_bin": peak, "iter_override_n": n_it + 1}, debug=True)
+    # the forced fit only changes the event holding that cluster, and only that vertex
+    assert int(forced.vertices[e, k]["n_iter"]) == n_it + 1
+    g = copy.deepcopy(forced)
+    o_small = copy.deepcopy(o)
+    o_small.vertices[e, k]["conv_margin"] = 1e-3
+    rep = parity.compare(b, g, o_small, debug=True)
+    assert rep.ok(), rep.problems
+    assert rep.iter_ties == 1
+    rep = parity.compare(b, g, o, debug=True)            # margin too large for a tie
+    assert not rep.ok() and any("n_iter" in m for m in rep.problems)
+    g_off = copy.deepcopy(g)
+    g_off.vertices[e, k]["z"] += 2e-3
+    rep = parity.compare(b, g_off, o_small, debug=True)
+    assert not rep.ok() and any("position" in m for m in rep.problems)
+
+
+def test_precut_tie_only_within_the_reported_band():
+    """Multi-vertex lists: a list one track longer is a tie only where the
+    oracle reports a track within tie_rel of the cut."""
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    o = _result(b, {"assoc_mode": 1})
+    e = int(np.nonzero(o.n_clusters > 0)[0][0])
+    g = copy.deepcopy(o)
+    g.clusters[e, 0]["n_assoc"] += 1
+    rep = parity.compare(b, g, o, debug=True, mv=True)
+    assert not rep.ok() and any("n_assoc" in m for m in rep.problems)
+    o_near = copy.deepcopy(o)
+    o_near.clusters[e, 0]["n_near_cut"] = 1
+    rep = parity.compare(b, g, o_near, debug=True, mv=True)
+    assert rep.ok(), rep.problems
+    assert rep.precut_ties == 1
+
+
+def test_track_reporting_no_vertex_is_a_tie_only_at_negligible_weight():
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    o = _result(b, {"assoc_mode": 1})
+    i = int(np.nonzero(o.track_vertex >= 0)[0][0])
+    g = copy.deepcopy(o)
+    g.track_vertex[i] = -1
+    g.track_weight[i] = 0.0
+    o_low = copy.deepcopy(o)
+    o_low.track_weight[i] = 3e-5
+    rep = parity.compare(b, g, o_low, debug=True, mv=True)
+    assert rep.ok(), rep.problems
+    rep = parity.compare(b, g, o, debug=True, mv=True)
+    assert not rep.ok()
