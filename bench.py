@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_14966_amd", "csrc", f)
                   for f in ("pvfind_kernels.hip", "pvfind_device.h", "pvfind_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pv_find_hbm_traffic.json")
+LDS_FILE = os.path.join(ROOT, "profiles", "pv_find_lds_traffic.json")
 
 
 def log(msg):
@@ -60,11 +61,123 @@ def latency_summary(comp, warm_frac=0.01):
             "achieved_events_per_s": round(len(comp) / span, 1)}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pv, batch, params, seconds):
+    """The oracle on the host cores: OpenMP over events on every thread it
+    may use, and on one thread, each on a bounded sample of the workload."""
+    import oracle
+    op = oracle.params_from_fields(pv.params_dict(params))
+    threads = oracle.max_threads()
+    done, passes, t1 = 0, 0, time.perf_counter()
+    while True:
+        oracle.find(batch, op, n_threads=threads)
+        done += batch.n_events
+        passes += 1
+        if time.perf_counter() - t1 >= seconds:
+            break
+    dt = time.perf_counter() - t1
+    # one thread: the first events of the workload, as many as ~seconds/4 take
+    n1 = min(batch.n_events, 500)
+    t2 = time.perf_counter()
+    oracle.find(batch.select(range(n1)), op, n_threads=1)
+    d1 = time.perf_counter() - t2
+    n_one = int(min(batch.n_events, max(n1, n1 * (seconds / 4.0) / max(d1, 1e-6))))
+    if n_one > n1:
+        t2 = time.perf_counter()
+        oracle.find(batch.select(range(n_one)), op, n_threads=1)
+        d1 = time.perf_counter() - t2
+    else:
+        n_one = n1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    cpu = {"value": round(done / dt, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+           "sample": f"{passes} pass(es) over the same {batch.n_events}-event workload, {dt:.1f} s wall, "
+                     f"OpenMP over events on {threads} threads",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "cpus_usable": affinity,
+           "one_core": {"value": round(n_one / d1, 1), "unit": "events/s", "cores": 1,
+                        "sample": f"the first {n_one} events of the workload, {d1:.1f} s wall"}}
+    log(f"cpu oracle: {cpu['value']} events/s on {threads} threads, {cpu['one_core']['value']} on one "
+        f"({cpu['cpu_model']})")
+    return cpu
+
+
+def end_to_end_leg(pv, batch, params, steps):
+    """The batched path with its PCIe transfers, as the paper's throughput
+    includes them: per step, the eight track columns and the offsets go from
+    pinned host memory to the device, pv_find runs, the written vertex
+    records are gathered into a dense array (pv_compact_vertices), and the
+    vertex counts, statuses, per-event record offsets and per-track outputs
+    come back, then the dense records (their total read from the first copy);
+    one stream, synchronised per step."""
+    import torch
+    ne, nt, mv = batch.n_events, batch.n_tracks, params.max_vertices_per_event
+    host_cols = [torch.from_numpy(np.ascontiguousarray(c)).pin_memory() for c in batch.fields()]
+    host_offs = torch.from_numpy(np.ascontiguousarray(batch.offsets, dtype=np.int32)).pin_memory()
+    db = pv.to_device(batch)
+    out = pv.alloc_outputs(db, mv)
+    dense = torch.empty(ne * mv * 64, dtype=torch.uint8, device=out.vertices.device)
+    first = torch.empty(ne + 1, dtype=torch.int32, device=out.vertices.device)
+    h_nv = torch.empty(ne, dtype=torch.int32).pin_memory()
+    h_st = torch.empty(ne, dtype=torch.int32).pin_memory()
+    h_first = torch.empty(ne + 1, dtype=torch.int32).pin_memory()
+    h_tv = torch.empty(nt, dtype=torch.int32).pin_memory()
+    h_tw = torch.empty(nt, dtype=torch.float32).pin_memory()
+    h_v = torch.empty(ne * mv * 64, dtype=torch.uint8).pin_memory()
+    stream = torch.cuda.current_stream()
+    moved = [0, 0]
+
+    def step():
+        for d, h in zip(db.cols, host_cols):
+            d.copy_(h, non_blocking=True)
+        db.offsets.copy_(host_offs, non_blocking=True)
+        pv.pv_find(db, out, params)
+        pv.pv_compact_vertices(out, ne, dense, first)
+        h_nv.copy_(out.n_vertices, non_blocking=True)
+        h_st.copy_(out.status, non_blocking=True)
+        h_first.copy_(first, non_blocking=True)
+        h_tv.copy_(out.track_vertex, non_blocking=True)
+        h_tw.copy_(out.track_weight, non_blocking=True)
+        stream.synchronize()
+        nbytes = 64 * int(h_first[ne])
+        h_v[:nbytes].copy_(dense[:nbytes], non_blocking=True)
+        stream.synchronize()
+        moved[0] = 32 * nt + 4 * (ne + 1)
+        moved[1] = 8 * ne + 4 * (ne + 1) + 8 * nt + nbytes
+
+    for _ in range(3):
+        step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    dt = (time.perf_counter() - t0) / steps
+    res = {"events_per_s": round(ne / dt, 1), "ms_per_step": round(dt * 1e3, 4), "h2d_bytes": moved[0],
+           "d2h_bytes": moved[1], "pcie_gbs": round((moved[0] + moved[1]) / dt / 1e9, 2),
+           "vertex_records": int(h_first[ne])}
+    log(f"end to end with H2D/D2H: {res['events_per_s']:.4g} events/s ({res['ms_per_step']:.3f} ms per step, "
+        f"{res['pcie_gbs']} GB/s over PCIe)")
+    del db, out, dense
+    return res
+
+
 def served_leg(pv, synth, n_events):
     """Continuous-batching server vs the plain one-launch-per-event server on
     the served mix (mu log-uniform in [1, 40]), host buffers in and out, so
     every figure includes the PCIe transfers."""
-    batch = synth.generate("served_mulog_200kev", n_events=n_events, keep_truth=False)
+    t0 = time.time()
+    batch = synth.generate_parallel("served_mulog_200kev", n_events=n_events, workers=8)
+    log(f"served mix: generated {batch.n_events} events / {batch.n_tracks} tracks in {time.time() - t0:.1f} s")
     params = pv.make_params({"max_vertices_per_event": 96})
     host = pv.HostEvents(batch, params.max_vertices_per_event)
     rng = np.random.default_rng(7)
@@ -165,8 +278,10 @@ def main():
                     help="waves,capacity,persistent,teams_per_cu (default: chosen by pv_autotune on the batch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--served-events", type=int, default=20000,
+    ap.add_argument("--served-events", type=int, default=200000,
                     help="events of the served mix replayed per offered rate (0 skips the served leg)")
+    ap.add_argument("--e2e-steps", type=int, default=10,
+                    help="steps of the PCIe-inclusive end-to-end leg (0 skips it)")
     ap.add_argument("--batched-configs", default="pp_mu5_gas_50kev,pp_mu40_20kev",
                     help="further batched workloads timed last, each under its own autotuned schedule "
                          "(empty skips them)")
@@ -275,11 +390,29 @@ def main():
         if (tf.get("kernel_sha") == kernel_hash() and tf.get("workload") == args.workload
                 and (tf.get("schedule") or [])[:2] == sched_key):
             traffic = tf.get("hbm_bytes_per_launch")
+    # the second bound: LDS bytes of the same launch (from the shader counters
+    # of a profiled run of this kernel source) against the LDS read bandwidth
+    # measured now by the library's microbenchmark
+    lds_peak_bs, lds_wg = pv.pv_measure_lds_peak()
+    lds = {"bound": "lds", "peak": round(lds_peak_bs / 1e9, 1), "unit": "GB/s",
+           "peak_source": f"pv_measure_lds_peak: {lds_wg} workgroups of 256 threads, 16-byte conflict-free reads",
+           "achieved": None, "frac": None, "lds_bytes_per_launch": None}
+    if os.path.exists(LDS_FILE):
+        with open(LDS_FILE) as f:
+            lf = json.load(f)
+        sched_key = [schedule["waves_per_team"], schedule["track_capacity"]]
+        if (lf.get("kernel_sha") == kernel_hash() and lf.get("workload") == args.workload
+                and (lf.get("schedule") or [])[:2] == sched_key):
+            lb = lf.get("lds_bytes_per_launch")
+            lds.update(lds_bytes_per_launch=lb, achieved=round(lb / (main_us * 1e-6) / 1e9, 1),
+                       frac=round(lb / (main_us * 1e-6) / lds_peak_bs, 4),
+                       bank_conflict_cycle_frac=lf.get("bank_conflict_cycle_frac"))
+    log(f"LDS read peak {lds['peak']} GB/s; main kernel LDS {lds['achieved']} GB/s")
     kname = f"pv_find_single<{schedule['waves_per_team']}, {schedule['track_capacity']}> (main fused launch)"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "algorithmic_bytes_per_launch": abytes,
-                "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2)}
+                "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2), "lds": lds}
 
     # the GPU variant of the association and fit (Eq. 18 weights over every
     # candidate), same batch and schedule, same timing
@@ -340,22 +473,9 @@ def main():
     # CPU oracle on a bounded sample (test infrastructure, timed as a baseline)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        op = oracle.params_from_fields(pv.params_dict(params))
-        threads = oracle.max_threads()
-        done, t1 = 0, time.perf_counter()
-        passes = 0
-        while True:
-            oracle.find(batch, op, n_threads=threads)
-            done += batch.n_events
-            passes += 1
-            if time.perf_counter() - t1 >= args.cpu_seconds:
-                break
-        dt = time.perf_counter() - t1
-        cpu = {"value": round(done / dt, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
-               "sample": f"{passes} pass(es) over the same {batch.n_events}-event workload, "
-                         f"{dt:.1f} s wall, OpenMP over events"}
-        log(f"cpu oracle: {cpu['value']} events/s on {threads} threads")
+        cpu = cpu_baseline(pv, batch, params, args.cpu_seconds)
+
+    e2e = end_to_end_leg(pv, batch, params, args.e2e_steps) if args.e2e_steps > 0 else None
 
     served = None
     if args.served_events > 0:
@@ -373,7 +493,7 @@ def main():
         "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
                    "n_vertices": nv, "schedule": schedule},
         "step_us": step_us, "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event,
-        "multivertex": multivertex, "served": served, "batched_configs": batched_configs,
+        "multivertex": multivertex, "end_to_end_pcie": e2e, "served": served, "batched_configs": batched_configs,
     }
     print(json.dumps(line), flush=True)
 

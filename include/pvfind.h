@@ -267,6 +267,23 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
                 const char *cache_path, const char *key, int32_t force, pv_schedule *best,
                 double *best_us, void *stream);
 
+/* Output compaction for transfers.  pv_find writes each event's vertices
+ * into max_vertices slots; most stay unused (about 5 vertices per event at
+ * mu = 5 against 128 slots).  This gathers the written records of a batch
+ * into one dense array so that only they need to cross PCIe:
+ *  slots, n_vertices : device outputs of pv_find for n_events events with
+ *                      max_vertices (1..128) slots each (counts are clamped
+ *                      to [0, max_vertices]).
+ *  dense             : device, room for first[n_events] records (at most
+ *                      n_events * max_vertices); event e's records land at
+ *                      dense[first[e] .. first[e + 1]).
+ *  first             : device int32[n_events + 1], written: exclusive prefix of
+ *                      the counts, first[n_events] = total.
+ * Two launches on `stream` (a one-workgroup scan, then the copy); no
+ * allocation.  The caller reads first[n_events] back to size its copy. */
+int pv_compact_vertices(const pv_vertex *slots, const int32_t *n_vertices, int32_t n_events,
+                        int32_t max_vertices, pv_vertex *dense, int32_t *first, void *stream);
+
 /* Replace / read the default schedule used by pv_find (process-wide). */
 int pv_set_schedule(const pv_schedule *schedule);
 int pv_get_schedule(pv_schedule *schedule);
@@ -280,6 +297,15 @@ int pv_get_schedule(pv_schedule *schedule);
  * output pointer may be NULL). */
 int pv_timing_start(void);
 int pv_timing_stop(double *main_ms, double *large_ms, int64_t *n_calls);
+
+/* Benchmark support: the LDS read bandwidth of the current device, the peak
+ * the kernels' LDS traffic is compared with.  Two workgroups per compute unit
+ * (64 KiB of LDS each) read 16 bytes per lane per step, without bank
+ * conflicts, 4096 steps; the best of three timed launches (HIP events on
+ * `stream`, after one warm-up) gives *bytes_per_s; *workgroups (may be NULL)
+ * receives the grid size.  Allocates and frees a small device buffer;
+ * synchronises `stream`. */
+int pv_measure_lds_peak(double *bytes_per_s, int32_t *workgroups, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of events that arrive one at a time.

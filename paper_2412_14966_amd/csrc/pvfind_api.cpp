@@ -158,6 +158,16 @@ int derive_params(const pv_params *p, const pv_beamline *bl, pvk::KParams &k)
     k.z_max = p->z_max;
     k.dz = p->dz;
     k.inv_dz = 1.0f / p->dz;
+    {
+        int ex = 0;
+        k.dz_pow2 = (std::frexp(p->dz, &ex) == 0.5f) ? 1 : 0;
+    }
+    k.edges_exact = 1;
+    for (int j = 0; j <= nb && k.edges_exact; ++j) {
+        const double jd = (double)j * (double)p->dz, e = (double)p->z_min + jd;
+        if ((double)(float)jd != jd || (double)(float)e != e)
+            k.edges_exact = 0;
+    }
     k.u0 = p->u0;
     k.sigma_max_pp = p->sigma_max_pp;
     k.sigma_max_gas = p->sigma_max_gas;
@@ -261,9 +271,9 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         return PV_OK;
     int32_t *order = nullptr;
     rc = get_workspace(stream, n_events, &A.wq, &order);
-    A.order = (s.persistent >= 3) ? order : nullptr;
     if (rc != PV_OK)
         return rc;
+    A.order = (s.persistent >= 3) ? order : nullptr;
     A.x = tracks->x;
     A.y = tracks->y;
     A.z = tracks->z;
@@ -289,7 +299,7 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         A.dbg_bin = dbg->bin;
         A.dbg_cycles = dbg->stage_cycles;
     }
-    bool timing;
+    bool timing = false;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
         timing = g_timing;

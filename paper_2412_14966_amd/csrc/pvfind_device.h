@@ -204,7 +204,10 @@ __device__ __forceinline__ Proj project(float x, float y, float z, float tx, flo
     r.sg = sg;
     if (!(zp >= p.z_min && zp < p.z_max))
         return r;
-    int b = (int)floorf((zp - p.z_min) / p.dz);
+    // the bin is floor of a correctly rounded quotient; when dz is a power
+    // of two the product with 1 / dz is that same quotient, exactly
+    const float q = p.dz_pow2 ? (zp - p.z_min) * p.inv_dz : (zp - p.z_min) / p.dz;
+    int b = (int)floorf(q);
     b = min(max(b, 0), p.nb - 1);
     r.bin = b;
     r.fl = kTrAssoc;
@@ -218,6 +221,15 @@ __device__ __forceinline__ Proj project(float x, float y, float z, float tx, flo
 // ---------------------------------------------------------------------------
 // Sec. 3.2: kernel mass left of a bin edge, cubic cumulative, fixed point
 // ---------------------------------------------------------------------------
+// P * unit rounded to the nearest integer, ties to even: P * unit is exact
+// (unit = 2^frac_bits, frac_bits <= 18, P in [0, 1]), so the fused
+// multiply-add with 1.5 * 2^23 rounds the exact product once, to an integer
+// held in the low mantissa bits
+__device__ __forceinline__ int fixed_code(float P, float unit)
+{
+    return __float_as_int(__builtin_fmaf(P, unit, 12582912.0f)) - 0x4B400000;
+}
+
 // r = 1 / (u0 sigma), correctly rounded, once per track
 __device__ __forceinline__ int edge_code(float e, float zp, float r, float unit)
 {
@@ -226,8 +238,8 @@ __device__ __forceinline__ int edge_code(float e, float zp, float r, float unit)
         s = -1.0f;
     if (s > 1.0f)
         s = 1.0f;
-    const float P = 0.5f + s * (0.75f - 0.25f * (s * s));
-    return (int)rintf(P * unit);
+    const float P = 0.5f + s * __builtin_fmaf(-0.25f, s * s, 0.75f);
+    return fixed_code(P, unit);
 }
 
 // Window of edges [jl, jh] whose codes are computed for a track at zp with
@@ -263,21 +275,48 @@ constexpr int kShortWindow = 8;   // bins per lane in the per-lane pass
 // edge beyond the kernel's support, and the codes grow with the edge), so
 // those edges are set to `unit` without evaluation and add nothing.
 // hist[j + off] holds bin j.
-__device__ __forceinline__ int edge_code_in(int j, float zp, float r, const KParams &p)
+// code of edge e (its z) for a track at zp with r = 1 / (u0 sigma).  The
+// cubic's inner term 0.75 - 0.25 s^2 is one fused multiply-add: 0.25 s^2 is
+// exact (a power-of-two scaling; below the normal range it is far under half
+// an ulp of 0.75 either way), so the single rounding equals the two.
+__device__ __forceinline__ int edge_code_z(float e, float zp, float r, const KParams &p)
 {
-    const float e = p.z_min + (float)j * p.dz;
     // clamp to [-1, 1]; s is finite here (zp and r are)
     const float s = __builtin_amdgcn_fmed3f((e - zp) * r, -1.0f, 1.0f);
-    const float P = 0.5f + s * (0.75f - 0.25f * (s * s));
-    return (int)rintf(P * p.unit);
+    const float P = 0.5f + s * __builtin_fmaf(-0.25f, s * s, 0.75f);
+    return fixed_code(P, p.unit);
 }
 
+__device__ __forceinline__ int edge_code_in(int j, float zp, float r, const KParams &p)
+{
+    return edge_code_z(p.z_min + (float)j * p.dz, zp, r, p);
+}
+
+template <int T = kShortWindow>
 __device__ __forceinline__ void fill_short(int *hist, int off, Window w, float zp, float r, const KParams &p)
 {
     const int full = (int)p.unit;
+    if (p.edges_exact) {
+        // every edge z_min + j dz is exact in binary32, so edge j + 1 is edge j
+        // plus dz, exactly
+        float e = p.z_min + (float)w.jl * p.dz;
+        int prev = (w.jl <= 0) ? 0 : edge_code_z(e, zp, r, p);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const int j = w.jl + u;
+            e += p.dz;
+            const int c = edge_code_z(e, zp, r, p);
+            const int next = (j + 1 >= w.jh) ? full : c;
+            const int d = next - prev;
+            if (d != 0)
+                atomicAdd(&hist[j + off], d);
+            prev = next;
+        }
+        return;
+    }
     int prev = (w.jl <= 0) ? 0 : edge_code_in(w.jl, zp, r, p);
 #pragma unroll
-    for (int u = 0; u < kShortWindow; ++u) {
+    for (int u = 0; u < T; ++u) {
         const int j = w.jl + u;
         const int c = edge_code_in(j + 1, zp, r, p);
         const int next = (j + 1 >= w.jh) ? full : c;
@@ -662,6 +701,48 @@ __device__ __forceinline__ T inverse_a(T a, T b, T c, T d, T out[6])
     out[4] = (a * c) * r;           // yz
     out[5] = (a * a) * r;           // zz
     return det;
+}
+
+// C = J C' J^T for x = e_x + t_x z, y = e_y + t_y z: the covariance of
+// (x, y, z) from that of (e_x, e_y, z) (packed xx, xy, yy, xz, yz, zz).
+template <typename T>
+__device__ __forceinline__ void map_covariance(const T cp[6], T tx, T ty, T c[6])
+{
+    c[5] = cp[5];
+    c[3] = cp[3] + tx * cp[5];
+    c[4] = cp[4] + ty * cp[5];
+    c[0] = cp[0] + tx * (T(2) * cp[3] + tx * cp[5]);
+    c[1] = cp[1] + tx * (cp[4] + ty * cp[5]) + ty * cp[3];
+    c[2] = cp[2] + ty * (T(2) * cp[4] + ty * cp[5]);
+}
+
+// Covariance of a fitted vertex (Eq. 14).  The fit works with a reference
+// slope t_ref (the mean of its tracks' slopes): unknowns e = (x, y) - z t_ref
+// and slopes t - t_ref, whose normal matrix A' has a = s0, b = sx', c = sy',
+// d = szz'.  C' = A'^-1 is mapped back to (x, y, z).  The 1-norm condition
+// number is that of the normal matrix A of (x, y, z) (b = sx' + s0 t_x,
+// c = sy' + s0 t_y, d = szz' + 2 t_ref . s' + s0 |t_ref|^2); above `cond`
+// the inversion and the map are redone in binary64 (the return value).
+__device__ __forceinline__ bool vertex_covariance(float la, float lb, float lc, float ld, float trx, float try_,
+                                                  float cond, float cf[6])
+{
+    float cp[6];
+    const float det = inverse_a<float>(la, lb, lc, ld, cp);
+    map_covariance<float>(cp, trx, try_, cf);
+    const float b = fmaf(la, trx, lb), c = fmaf(la, try_, lc);
+    const float d = fmaf(la, fmaf(trx, trx, try_ * try_), fmaf(2.0f, fmaf(trx, lb, try_ * lc), ld));
+    const float na = fmaxf(fmaxf(la + fabsf(b), la + fabsf(c)), fabsf(b) + fabsf(c) + d);
+    const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]), fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
+                           fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
+    if (!(det > 0.0f) || !(na * ni <= cond)) {
+        double cd[6], cm[6];
+        inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
+        map_covariance<double>(cd, (double)trx, (double)try_, cm);
+        for (int q = 0; q < 6; ++q)
+            cf[q] = (float)cm[q];
+        return true;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------------------

@@ -36,6 +36,8 @@ struct KParams {
     float e_max_mv;             // exp(-chi2_max_mv / 2)
     float chi2_window_mv, conv_dz_mv, dup_ratio, w_count_mv;
     int peak_rec;               // x86 splitting of proto-clusters (Sec. 3.3)
+    int dz_pow2;                // dz is a power of two: x / dz == x * inv_dz exactly
+    int edges_exact;            // every bin edge z_min + j dz (0 <= j <= nb) is exact in binary32
 };
 
 // Device workspace of one stream: work-queue counters, the list of events

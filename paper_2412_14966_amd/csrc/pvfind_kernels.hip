@@ -37,12 +37,13 @@
 namespace pvk {
 
 // Fit state of the live vertices: position relative to the frame, the last
-// normal matrix (a, b, c, d as in Eq. 14) and n_iter | not_converged << 8 |
-// failed << 9.
+// normal matrix (a, b, c, d as in Eq. 14, of the slopes relative to the
+// reference slope tx, ty) and n_iter | not_converged << 8 | failed << 9.
 template <int V>
 struct VertexFit {
     float dx[V], dy[V], dz[V];
     float a[V], b[V], c[V], d[V];
+    float tx[V], ty[V];   // reference slope of the fit (normal matrix a..d is that of the shifted slopes)
     int info[V];
 };
 
@@ -294,9 +295,41 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
                     rO[u] = 0.0f;
             }
         }
+        // Reference slope: the mean of the vertex's track slopes.  The fit's
+        // unknowns are e = (dx, dy) - dz t_ref and dz, its slopes t - t_ref:
+        // residuals, chi2 and the step's chi2 change are those of (dx, dy, dz),
+        // but the normal matrix holds no cancellation between s0 szz and
+        // sx^2 + sy^2 when the slopes are alike, which in binary32 moved
+        // vertices of a few tracks by micrometres.
+        float trx = 0.0f, try_ = 0.0f;
+        {
+            float ts[2] = {0.0f, 0.0f};
+#pragma unroll
+            for (int u = 0; u < kRegTracks; ++u) {
+                ts[0] += rTX[u];
+                ts[1] += rTY[u];
+            }
+            for (int t = gl + kRegTracks * L; t < ck; t += L) {
+                ts[0] += S.u.f.TX[beg + t];
+                ts[1] += S.u.f.TY[beg + t];
+            }
+            if (prop)
+                group_sum_n_var_rt<2>(ts, L, lgmax);
+            else
+                group_sum_n_rt<2>(ts, lg);
+            const float inv_n = (ck > 0) ? __builtin_amdgcn_rcpf((float)ck) : 0.0f;
+            trx = ts[0] * inv_n;
+            try_ = ts[1] * inv_n;
+#pragma unroll
+            for (int u = 0; u < kRegTracks; ++u) {
+                rTX[u] -= trx;
+                rTY[u] -= try_;
+            }
+        }
         // start at the seed: on the beamline, delta dz above the bin centre
         const float d0 = has ? S.cd0[S.live[k]] : 0.0f;
-        float dx = p.btx * d0, dy = p.bty * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f, ld = 0.0f;
+        float dx = (p.btx - trx) * d0, dy = (p.bty - try_) * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f,
+              ld = 0.0f;
         int nit = 0;
         bool active = has, failed = false, conv = false;
         for (int it = 1; it <= p.max_iter; ++it) {
@@ -317,10 +350,11 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
                     const float wt = S.u.f.WT[sl];
                     if (wt > 0.0f) {
                         if constexpr (MV)
-                            accumulate_mv(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, S.u.f.OTH[sl],
-                                          dx, dy, dz, p);
+                            accumulate_mv(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl] - trx, S.u.f.TY[sl] - try_, wt,
+                                          S.u.f.OTH[sl], dx, dy, dz, p);
                         else
-                            accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl], S.u.f.TY[sl], wt, dx, dy, dz, p);
+                            accumulate(a, S.u.f.X[sl], S.u.f.Y[sl], S.u.f.TX[sl] - trx, S.u.f.TY[sl] - try_, wt, dx,
+                                       dy, dz, p);
                     }
                 }
             }
@@ -331,10 +365,13 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
                 group_sum_n_rt<7>(r, lg);
             const float s0 = r[0], sx = r[1], sy = r[2], szz = r[3], gx = r[4], gy = r[5], gz = r[6];
             if (active) {
-                // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz);
-                // det(A) = s0 * D, singular when det <= sing_ratio * s0 * s0 * szz
+                // A = [[s0, 0, -sx], [0, s0, -sy], [-sx, -sy, szz]], half-gradient (-gx, -gy, gz),
+                // in the shifted slopes; det(A) = s0 * D is the same for the slopes
+                // themselves, singular when det <= sing_ratio * s0 * s0 * szz with szz
+                // that of the slopes themselves
                 const float D = fmaf(s0, szz, -fmaf(sx, sx, sy * sy));
-                if (!(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz))) {
+                const float szz_t = fmaf(s0, fmaf(trx, trx, try_ * try_), fmaf(2.0f, fmaf(trx, sx, try_ * sy), szz));
+                if (!(s0 > 0.0f) || !(D > p.sing_ratio * (s0 * szz_t))) {
                     failed = true;
                     active = false;
                 } else {
@@ -361,13 +398,16 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
             }
         }
         if (has && gl == 0) {
-            S.vf.dx[k] = dx;
-            S.vf.dy[k] = dy;
+            // back to the frame's transverse offsets: (dx, dy) = e + dz t_ref
+            S.vf.dx[k] = fmaf(dz, trx, dx);
+            S.vf.dy[k] = fmaf(dz, try_, dy);
             S.vf.dz[k] = dz;
             S.vf.a[k] = la;
             S.vf.b[k] = lb;
             S.vf.c[k] = lc;
             S.vf.d[k] = ld;
+            S.vf.tx[k] = trx;
+            S.vf.ty[k] = try_;
             S.vf.info[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
         }
     }
@@ -435,22 +475,10 @@ __device__ __forceinline__ void final_pass(Smem<W, CAP, BIG, MV> &S, const KArgs
         if (has && gl == 0 && vo >= 0) {
             const int cq = S.live[k];
             const float zr = bin_centre(S.cpk[cq], p);
-            const float la = S.vf.a[k], lb = S.vf.b[k], lc = S.vf.c[k], ld = S.vf.d[k];
             float cf[6];
-            const float det = inverse_a<float>(la, lb, lc, ld, cf);
-            // 1-norm condition number of A
-            const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
-            const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
-                                         fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
-                                   fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
             int flags = (S.vf.info[k] & kInfoNotConv) ? PV_VX_NOT_CONVERGED : 0;
-            if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
-                double cd[6];
-                inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
-                for (int q = 0; q < 6; ++q)
-                    cf[q] = (float)cd[q];
+            if (vertex_covariance(S.vf.a[k], S.vf.b[k], S.vf.c[k], S.vf.d[k], S.vf.tx[k], S.vf.ty[k], p.cond_fp64, cf))
                 flags |= PV_VX_FP64_INVERSION;
-            }
             pv_vertex v;
             v.x = (p.bx + p.btx * zr) + dx;
             v.y = (p.by + p.bty * zr) + dy;
@@ -1187,18 +1215,9 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 c = group_sum_rt(c, L);
                 if (has && gl == 0) {
                     S.ntk[k] = (int)c;
-                    const float la = S.vf.a[k], lb = S.vf.b[k], lc = S.vf.c[k], ld = S.vf.d[k];
                     float cf[6];
-                    const float det = inverse_a<float>(la, lb, lc, ld, cf);
-                    const float na = fmaxf(fmaxf(la + fabsf(lb), la + fabsf(lc)), fabsf(lb) + fabsf(lc) + ld);
-                    const float ni = fmaxf(fmaxf(fabsf(cf[0]) + fabsf(cf[1]) + fabsf(cf[3]),
-                                                 fabsf(cf[1]) + fabsf(cf[2]) + fabsf(cf[4])),
-                                           fabsf(cf[3]) + fabsf(cf[4]) + fabsf(cf[5]));
-                    if (!(det > 0.0f) || !(na * ni <= p.cond_fp64)) {
-                        double cd[6];
-                        inverse_a<double>((double)la, (double)lb, (double)lc, (double)ld, cd);
-                        cf[5] = (float)cd[5];
-                    }
+                    vertex_covariance(S.vf.a[k], S.vf.b[k], S.vf.c[k], S.vf.d[k], S.vf.tx[k], S.vf.ty[k],
+                                      p.cond_fp64, cf);
                     S.czz[k] = cf[5];
                 }
             }
@@ -1380,27 +1399,52 @@ __global__ __launch_bounds__(64 * W, (small_waves_per_simd<W, CAP, MV>())) void 
 // ---------------------------------------------------------------------------
 constexpr int kOrderBuckets = 256;
 
+constexpr int kOrderPerThread = 16;   // events per thread and pass
+
 __global__ __launch_bounds__(1024) void order_events_kernel(const int32_t *offsets, const int32_t *n_events_dev,
                                                             int32_t n_events_host, int32_t *order)
 {
     __shared__ int cnt[kOrderBuckets];
+    const int tid = threadIdx.x;
     const int n_events = n_events_dev ? *n_events_dev : n_events_host;
     const int total = offsets[n_events];
-    auto bucket = [&](int e) -> int {
-        const int a = offsets[e], b = offsets[e + 1];
-        if (a < 0 || b < a || b > total)
-            return 0;
-        return min((b - a) >> 4, kOrderBuckets - 1);
+    constexpr int kChunk = 1024 * kOrderPerThread;
+    // bucket of each of this thread's events of the chunk starting at c0 (-1:
+    // none); all the offset loads are issued before any is used
+    auto buckets = [&](int c0, int bk[kOrderPerThread]) __attribute__((always_inline)) {
+        int lo[kOrderPerThread], hi[kOrderPerThread];
+#pragma unroll
+        for (int u = 0; u < kOrderPerThread; ++u) {
+            const int e = c0 + tid + 1024 * u;
+            lo[u] = (e < n_events) ? offsets[e] : 0;
+            hi[u] = (e < n_events) ? offsets[e + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderPerThread; ++u) {
+            const int e = c0 + tid + 1024 * u;
+            const int a = lo[u], b = hi[u];
+            bk[u] = (e >= n_events) ? -1 : ((a < 0 || b < a || b > total) ? 0 : min((b - a) >> 4, kOrderBuckets - 1));
+        }
     };
-    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x)
+    for (int k = tid; k < kOrderBuckets; k += blockDim.x)
         cnt[k] = 0;
     __syncthreads();
-    for (int e = threadIdx.x; e < n_events; e += blockDim.x)
-        atomicAdd(&cnt[bucket(e)], 1);
+    int first[kOrderPerThread];   // the first chunk's buckets, kept for the second pass
+    for (int c0 = 0; c0 < n_events; c0 += kChunk) {
+        int bk[kOrderPerThread];
+        buckets(c0, bk);
+#pragma unroll
+        for (int u = 0; u < kOrderPerThread; ++u) {
+            if (bk[u] >= 0)
+                atomicAdd(&cnt[bk[u]], 1);
+            if (c0 == 0)
+                first[u] = bk[u];
+        }
+    }
     __syncthreads();
     // exclusive prefix over the buckets, largest first: one wavefront
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
+    if (tid < 64) {
+        const int lane = tid;
         int run = 0;
         for (int k0 = kOrderBuckets - 64; k0 >= 0; k0 -= 64) {
             const int k = k0 + 63 - lane;   // lane 0 takes the largest bucket of the chunk
@@ -1411,17 +1455,25 @@ __global__ __launch_bounds__(1024) void order_events_kernel(const int32_t *offse
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n_events; e += blockDim.x)
-        order[atomicAdd(&cnt[bucket(e)], 1)] = e;
+    for (int c0 = 0; c0 < n_events; c0 += kChunk) {
+        int bk[kOrderPerThread];
+        if (c0 == 0) {
+#pragma unroll
+            for (int u = 0; u < kOrderPerThread; ++u)
+                bk[u] = first[u];
+        } else {
+            buckets(c0, bk);
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderPerThread; ++u)
+            if (bk[u] >= 0)
+                order[atomicAdd(&cnt[bk[u]], 1)] = c0 + tid + 1024 * u;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-struct DevInfo {
-    int cus = 0;
-};
-
 static int device_cus()
 {
     // per thread: the server's worker thread and callers may launch concurrently

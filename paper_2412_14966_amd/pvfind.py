@@ -91,6 +91,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2412_14966_amd.build")
+        # torch first: it loads its own copy of the HIP runtime under the same
+        # soname, and libpvfind must bind to that copy.  Loaded the other way
+        # round, the process holds two HIP runtimes and the second one to
+        # touch the GPU finds no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         vp = ctypes.c_void_p
@@ -112,6 +117,8 @@ def lib():
         L.pv_get_schedule.argtypes = [P(pv_schedule)]
         L.pv_timing_start.argtypes = []
         L.pv_timing_stop.argtypes = [P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int64)]
+        L.pv_measure_lds_peak.argtypes = [P(ctypes.c_double), P(ctypes.c_int32), vp]
+        L.pv_compact_vertices.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
         L.pv_last_error.restype = ctypes.c_char_p
         L.pv_version.restype = ctypes.c_char_p
         _lib = L
@@ -167,6 +174,24 @@ def pv_get_schedule() -> pv_schedule:
 
 def pv_timing_start():
     _check(lib().pv_timing_start())
+
+
+def pv_compact_vertices(out: "Outputs", n_events: int, dense, first, stream=None):
+    """Gather the written vertex records of `out` into `dense` (uint8 device
+    tensor of at least 64 * n_events * max_vertices bytes); `first` (int32
+    device tensor of n_events + 1) receives the per-event offsets and total."""
+    st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
+    _check(lib().pv_compact_vertices(ctypes.c_void_p(out.vertices.data_ptr()), ctypes.c_void_p(out.n_vertices.data_ptr()),
+                                     n_events, out.max_vertices, ctypes.c_void_p(dense.data_ptr()),
+                                     ctypes.c_void_p(first.data_ptr()), st))
+
+
+def pv_measure_lds_peak(stream=None):
+    """(LDS read bandwidth in bytes/s, workgroups of the probe launch)."""
+    bw, wg = ctypes.c_double(), ctypes.c_int32()
+    st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
+    _check(lib().pv_measure_lds_peak(ctypes.byref(bw), ctypes.byref(wg), st))
+    return bw.value, wg.value
 
 
 def pv_timing_stop():

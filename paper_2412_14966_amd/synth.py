@@ -227,6 +227,28 @@ def generate(workload: str = "pp_mu5_100ev", n_events: Optional[int] = None, fir
                       truth_ntracks=truth_nt if keep_truth else None, **arrays)
 
 
+def _generate_chunk(args):
+    workload, n, first, kw = args
+    return generate(workload, n_events=n, first_event=first, keep_truth=False, **kw)
+
+
+def generate_parallel(workload: str, n_events: Optional[int] = None, workers: int = 8,
+                      chunk: int = 5000, **kw) -> TrackBatch:
+    """``generate`` without truth, with chunks of events drawn in worker
+    processes.  Every event has its own seed, so the batch is identical to
+    ``generate(workload, n_events, keep_truth=False, **kw)``."""
+    if n_events is None:
+        n_events = WORKLOADS[workload]["n_events"]
+    jobs = [(workload, min(chunk, n_events - a), a, kw) for a in range(0, n_events, chunk)]
+    if workers <= 1 or len(jobs) <= 1:
+        parts = [_generate_chunk(j) for j in jobs]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+            parts = pool.map(_generate_chunk, jobs)
+    return concat(parts) if parts else generate(workload, n_events=0, keep_truth=False, **kw)
+
+
 def from_tracks(events: Sequence[np.ndarray], beamline=(0.0, 0.0, 0.0, 0.0)) -> TrackBatch:
     """Build a batch from explicit per-event (n, 8) arrays of track states
     (columns in TRACK_FIELDS order).  Used for hand-made edge cases."""

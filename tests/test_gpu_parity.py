@@ -123,6 +123,60 @@ def test_adversarial_events():
     check(b, name="adversarial")
 
 
+def _ill_conditioned_event(zs, n, rng, slope_sd=3e-4, sxy=1e-4):
+    """Vertices on the beamline whose tracks have slopes of order slope_sd:
+    z is weakly constrained, so the normal matrix A of Eq. 11 has a 1-norm
+    condition number of about 1 / <t^2>, 4e6-9e6 here; sxy = 1e-4 mm keeps
+    sigma_poca = sxy / |t| below the 1.5 mm histogram cut."""
+    rows = []
+    for z in zs:
+        t = rng.normal(0.0, slope_sd, (n, 2))
+        dz = rng.uniform(-2.0, 2.0, n)
+        x = t[:, 0] * dz + rng.normal(0.0, sxy, n)
+        y = t[:, 1] * dz + rng.normal(0.0, sxy, n)
+        rows.append(np.stack([x, y, z + dz, t[:, 0], t[:, 1], np.full(n, sxy * sxy), np.zeros(n), np.zeros(n)], 1))
+    return np.concatenate(rows)
+
+
+def _kappa1(cov):
+    """1-norm condition number of A = C^-1 from a covariance record."""
+    c = np.asarray(cov, dtype=np.float64)
+    C = np.array([[c[0], c[1], c[3]], [c[1], c[2], c[4]], [c[3], c[4], c[5]]])
+    A = np.linalg.inv(C)
+    return np.abs(A).sum(0).max() * np.abs(C).sum(0).max()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["partition", "multivertex"])
+def test_fp64_covariance_inversion_on_ill_conditioned_clusters(mode):
+    """Eq. 14 in binary64 on the GPU where the condition number of A exceeds
+    cond_fp64 = 1e6: every vertex of the constructed events (kappa_1 4e6-9e6 by
+    the oracle's covariance) carries PV_VX_FP64_INVERSION, the vertices of
+    ordinary mu = 5 events (kappa_1 well below 1e6) do not, and all match the
+    oracle to the usual bars (covariance within COV_RTOL)."""
+    rng = np.random.default_rng(90)
+    ill = synth.from_tracks([_ill_conditioned_event((-100.0, 0.0, 150.0), 25, rng) for _ in range(20)])
+    b = synth.concat([ill, synth.generate("pp_mu5_100ev", n_events=30)])
+    prm = {"assoc_mode": mode}
+    g, o = run_both(b, prm, name=f"fp64 inversion, assoc_mode {mode}")
+    rep = parity.compare(b, g, o, debug=True, mv=bool(mode))
+    say(f"fp64 inversion: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+    assert rep.ties <= 2
+    n_ill = n_plain = 0
+    for e in range(b.n_events):
+        for k in range(int(o.n_vertices[e])):
+            kap = _kappa1(o.vertices[e, k]["cov"])
+            flagged = bool(g.vertices[e, k]["flags"] & pv.PV_VX_FP64_INVERSION)
+            if kap > 1.2e6:
+                assert flagged, (e, k, kap)
+                n_ill += 1
+            elif kap < 0.8e6:
+                assert not flagged, (e, k, kap)
+                n_plain += 1
+    say(f"fp64 inversion: {n_ill} vertices inverted in binary64, {n_plain} in binary32")
+    assert n_ill == 60 and n_plain > 100
+
+
 def test_events_larger_than_a_small_team_and_too_many_tracks():
     big = synth.generate("pp_mu40_20kev", n_events=6, mu=150.0)             # ~3900 tracks each
     sizes = np.diff(big.offsets)
@@ -262,6 +316,32 @@ def test_config3_beam_gas_sample():
 def test_config4_high_pileup_sample():
     b = synth.generate("pp_mu40_20kev", n_events=800, keep_truth=False)
     check(b, debug=True, name="mu=40 800 events")
+
+
+def _check_full_size_autotuned(workload, name):
+    """Every event of a workload compared with the oracle, run (without debug
+    outputs) under the schedule pv_autotune picks for that very batch, as
+    the benchmark times it."""
+    b = synth.generate(workload, keep_truth=False)
+    p = pv.pv_params_default()
+    db = pv.to_device(b)
+    out = pv.alloc_outputs(db, p.max_vertices_per_event)
+    before = pv.pv_get_schedule()
+    best, us = pv.pv_autotune(db, out, p, reps=3)
+    pv.pv_set_schedule(before.waves_per_team, before.track_capacity, before.persistent, before.teams_per_cu)
+    say(f"{name}: pv_autotune picks {best} ({us:.1f} us per launch)")
+    del db, out
+    return check(b, schedule=best, debug=False, name=f"{name} under {best}")
+
+
+def test_config3_beam_gas_full_size_autotuned():
+    """50,000 events at mu = 5 with beam-gas vertices."""
+    _check_full_size_autotuned("pp_mu5_gas_50kev", "pp + beam-gas 50k events")
+
+
+def test_config4_high_pileup_full_size_autotuned():
+    """20,000 events at mu = 40 (up to ~1,900 tracks per event)."""
+    _check_full_size_autotuned("pp_mu40_20kev", "mu=40 20k events")
 
 
 @pytest.mark.parametrize("cap", [1536, 2048])

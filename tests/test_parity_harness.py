@@ -82,3 +82,17 @@ def test_track_reporting_no_vertex_is_a_tie_only_at_negligible_weight():
     assert rep.ok(), rep.problems
     rep = parity.compare(b, g, o, debug=True, mv=True)
     assert not rep.ok()
+
+
+def test_weight_tail_is_counted_and_bounded():
+    """Weights may exceed W_TOL in at most max(2, 1e-6 n_tracks) tracks, and
+    never W_TAIL_TOL."""
+    b = synth.generate("pp_mu5_100ev", n_events=12)
+    o = _result(b, {})
+    idx = np.nonzero(o.track_vertex >= 0)[0]
+    for n_off, dw, ok in ((2, 5e-4, True), (3, 5e-4, False), (1, 2e-3, False)):
+        g = copy.deepcopy(o)
+        g.track_weight[idx[:n_off]] += dw
+        rep = parity.compare(b, g, o, debug=True)
+        assert rep.ok() == ok, (n_off, dw, rep.problems)
+        assert rep.w_tail == n_off
