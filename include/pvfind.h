@@ -230,6 +230,25 @@ int pv_find(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_eve
             const pv_beamline *beamline, const pv_params *params,
             pv_vertices_out *out_vertices, pv_track_out *out_track_weights, void *stream);
 
+/* pv_find for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, work and outputs as pv_find (default schedule), but the
+ * workspace is a fixed device array inside the library (one per device,
+ * about 2 MiB, held until the process ends) instead of memory the library
+ * allocates: no hipMalloc, hipFree or other allocating call is made.
+ *  n_events      : 0 .. PV_NOALLOC_MAX_EVENTS; more returns PV_EINVAL.
+ * All calls on one device share that array: calls that may overlap on one
+ * device (different streams, or different threads without ordering) race
+ * and give undefined results; calls on one stream are ordered by it.  Each
+ * call first zeroes the array's counters with a small kernel on `stream`
+ * (no memset), so a call may be captured into a graph.  The first call on a
+ * device looks the array's address up (hipGetSymbolAddress).  Calls made
+ * while pv_timing_start() is active are not timed. */
+#define PV_NOALLOC_MAX_EVENTS 262144
+int pv_find_noalloc(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                    const pv_beamline *beamline, const pv_params *params,
+                    pv_vertices_out *out_vertices, pv_track_out *out_track_weights, void *stream);
+
 /* pv_find with an explicit schedule (NULL = default).  Integer outputs (vertex
  * counts, track-to-vertex indices, histograms, clusters) do not depend on
  * the schedule; floating-point outputs are reproducible bit for bit for a

@@ -247,7 +247,7 @@ int get_workspace(void *stream, int n_events, pvk::WorkQueue **out, int32_t **or
 
 int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events, const pv_beamline *beamline,
               const pv_params *params, pv_vertices_out *ov, pv_track_out *ot, const pv_debug_out *dbg,
-              const pv_schedule *schedule, void *stream)
+              const pv_schedule *schedule, void *stream, bool noalloc = false)
 {
     if (!tracks || !offsets || !beamline || !params || !ov || !ot)
         return fail(PV_EINVAL, "null argument");
@@ -267,12 +267,23 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
     rc = validate_schedule(s);
     if (rc != PV_OK)
         return rc;
+    if (noalloc && n_events > PV_NOALLOC_MAX_EVENTS)
+        return fail(PV_EINVAL, "pv_find_noalloc: n_events %d exceeds PV_NOALLOC_MAX_EVENTS (%d)", n_events,
+                    PV_NOALLOC_MAX_EVENTS);
     if (n_events == 0)
         return PV_OK;
     int32_t *order = nullptr;
-    rc = get_workspace(stream, n_events, &A.wq, &order);
-    if (rc != PV_OK)
-        return rc;
+    if (noalloc) {
+        int herr = pvk::noalloc_workspace(&A.wq, &order);
+        if (herr == (int)hipSuccess)
+            herr = pvk::clear_queue(A.wq, stream);
+        if (herr != (int)hipSuccess)
+            return fail(PV_EHIP, "pv_find_noalloc workspace: %s", hipGetErrorString((hipError_t)herr));
+    } else {
+        rc = get_workspace(stream, n_events, &A.wq, &order);
+        if (rc != PV_OK)
+            return rc;
+    }
     A.order = (s.persistent >= 3) ? order : nullptr;
     A.x = tracks->x;
     A.y = tracks->y;
@@ -300,7 +311,7 @@ int find_impl(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events,
         A.dbg_cycles = dbg->stage_cycles;
     }
     bool timing = false;
-    {
+    if (!noalloc) {
         std::lock_guard<std::mutex> lk(g_tmu);
         timing = g_timing;
     }
@@ -411,6 +422,14 @@ int pv_find(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_eve
 {
     return find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights, nullptr,
                      nullptr, stream);
+}
+
+int pv_find_noalloc(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,
+                    const pv_beamline *beamline, const pv_params *params, pv_vertices_out *out_vertices,
+                    pv_track_out *out_track_weights, void *stream)
+{
+    return find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights, nullptr,
+                     nullptr, stream, true);
 }
 
 int pv_find_sched(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n_events,

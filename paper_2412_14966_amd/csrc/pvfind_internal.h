@@ -95,6 +95,12 @@ inline int32_t *order_list(WorkQueue *wq, int capacity)
     return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(wq) + offsetof(WorkQueue, big)) + capacity;
 }
 
+// Workspace of the allocation-free entry point on the current device (a
+// file-scope device array of the kernel file, PV_NOALLOC_MAX_EVENTS events),
+// and a launch that zeroes its counters on `stream`.  Return hipError_t values.
+int noalloc_workspace(WorkQueue **wq, int32_t **order);
+int clear_queue(WorkQueue *wq, void *stream);
+
 // Launch one batch on `stream` with schedule `s` (already validated).  With
 // `ev`, events are recorded around the launches.  Returns a hipError_t value.
 int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev);

@@ -34,6 +34,9 @@
 // four-wavefront teams holding 4096 tracks.
 #include "pvfind_device.h"
 
+#include <map>
+#include <mutex>
+
 namespace pvk {
 
 // Fit state of the live vertices: position relative to the frame, the last
@@ -1489,6 +1492,57 @@ static int device_cus()
         cached_cus = cus;
     }
     return cached_cus;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point (pv_find_noalloc): one
+// file-scope device array per device, holding the work-queue header, the
+// deferred-event list and the event order for up to PV_NOALLOC_MAX_EVENTS
+// events.  On the host the array's name is not a device address: host code
+// uses only the address hipGetSymbolAddress returns for the current device,
+// looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = offsetof(WorkQueue, big) + 2 * sizeof(int32_t) * (size_t)PV_NOALLOC_MAX_EVENTS;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int noalloc_workspace(WorkQueue **wq, int32_t **order)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;   // device -> address of its copy of `scratch`
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return (int)err;
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = addr.find(dev);
+        if (it == addr.end()) {
+            err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (err != hipSuccess)
+                return (int)err;
+            addr.emplace(dev, ptr);
+        } else {
+            ptr = it->second;
+        }
+    }
+    *wq = static_cast<WorkQueue *>(ptr);
+    *order = order_list(*wq, PV_NOALLOC_MAX_EVENTS);
+    return (int)hipSuccess;
+}
+
+// the work-queue counters start every allocation-free call at zero (a kernel
+// rather than a memset, so that the call may be captured in a graph)
+__global__ void clear_queue_kernel(WorkQueue *wq)
+{
+    if (threadIdx.x < offsetof(WorkQueue, big) / sizeof(unsigned int))
+        reinterpret_cast<unsigned int *>(wq)[threadIdx.x] = 0u;
+}
+
+int clear_queue(WorkQueue *wq, void *stream)
+{
+    hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), wq);
+    return (int)hipGetLastError();
 }
 
 template <int W, int CAP, bool MV, bool DEBUG>

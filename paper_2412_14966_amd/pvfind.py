@@ -106,6 +106,7 @@ def lib():
         common = [P(pv_tracks), vp, ctypes.c_int32, P(pv_beamline), P(pv_params), P(pv_vertices_out),
                   P(pv_track_out)]
         L.pv_find.argtypes = common + [vp]
+        L.pv_find_noalloc.argtypes = common + [vp]
         L.pv_find_sched.argtypes = common + [P(pv_schedule), vp]
         L.pv_find_debug.argtypes = common + [P(pv_debug_out), P(pv_schedule), vp]
         for f in (L.pv_find, L.pv_find_sched, L.pv_find_debug):
@@ -262,6 +263,18 @@ def pv_find(db: DeviceBatch, out: Outputs, params: pv_params, stream=None):
     st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
     _check(lib().pv_find(ctypes.byref(tr), ctypes.c_void_p(db.offsets.data_ptr()), db.n_events, ctypes.byref(bl),
                          ctypes.byref(params), ctypes.byref(ov), ctypes.byref(ot), st))
+
+
+PV_NOALLOC_MAX_EVENTS = 262144
+
+
+def pv_find_noalloc(db: DeviceBatch, out: Outputs, params: pv_params, stream=None):
+    """Enqueue pv_find_noalloc (no device allocation; at most
+    PV_NOALLOC_MAX_EVENTS events; calls overlapping on one device race)."""
+    tr, bl, ov, ot = _args(db, out, params)
+    st = ctypes.c_void_p(stream) if stream is not None else _current_stream()
+    _check(lib().pv_find_noalloc(ctypes.byref(tr), ctypes.c_void_p(db.offsets.data_ptr()), db.n_events,
+                                 ctypes.byref(bl), ctypes.byref(params), ctypes.byref(ov), ctypes.byref(ot), st))
 
 
 def pv_find_sched(db: DeviceBatch, out: Outputs, params: pv_params, schedule: pv_schedule, stream=None):

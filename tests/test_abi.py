@@ -123,6 +123,24 @@ def test_negative_event_count_and_bad_schedule_rejected():
         assert _call(schedule=pv.pv_schedule(2, 512, disabled, 0)) == pv.PV_EINVAL
 
 
+def test_noalloc_rejects_batches_beyond_its_workspace():
+    """pv_find_noalloc holds PV_NOALLOC_MAX_EVENTS events; a larger batch is
+    refused before anything is launched, a zero-event call is a no-op."""
+    L = pv.lib()
+    fake = 0x1000
+    tr = pv.pv_tracks(*([fake] * 8))
+    bl = pv.pv_beamline(0, 0, 0, 0)
+    ov = pv.pv_vertices_out(fake, fake, fake)
+    ot = pv.pv_track_out(fake, fake)
+    p = pv.pv_params_default()
+    for n, want in ((pv.PV_NOALLOC_MAX_EVENTS + 1, pv.PV_EINVAL), (-1, pv.PV_EINVAL), (0, pv.PV_OK)):
+        rc = L.pv_find_noalloc(ctypes.byref(tr), ctypes.c_void_p(fake), n, ctypes.byref(bl), ctypes.byref(p),
+                               ctypes.byref(ov), ctypes.byref(ot), None)
+        assert rc == want, (n, rc)
+        if n > 0:
+            assert "PV_NOALLOC_MAX_EVENTS" in pv.pv_last_error()
+
+
 def test_zero_events_is_a_no_op():
     assert _call(n_events=0) == pv.PV_OK
 
