@@ -101,6 +101,12 @@ inline int32_t *order_list(WorkQueue *wq, int capacity)
 int noalloc_workspace(WorkQueue **wq, int32_t **order);
 int clear_queue(WorkQueue *wq, void *stream);
 
+// Gather the written vertex records of n_events events (read from
+// n_events_dev when set, n_events its upper bound) into `dense`, with the
+// per-event offsets and total in first[0 .. n_events].  Returns a hipError_t.
+int launch_compact(const pv_vertex *slots, const int32_t *nv, const int32_t *n_events_dev, int n_events, int max_v,
+                   pv_vertex *dense, int32_t *first, void *stream);
+
 // Launch one batch on `stream` with schedule `s` (already validated).  With
 // `ev`, events are recorded around the launches.  Returns a hipError_t value.
 int launch_batch(const KArgs &args, const pv_schedule &s, bool debug, void *stream, LaunchEvents *ev);

@@ -329,6 +329,7 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
                 rTY[u] -= try_;
             }
         }
+
         // start at the seed: on the beamline, delta dz above the bin centre
         const float d0 = has ? S.cd0[S.live[k]] : 0.0f;
         float dx = (p.btx - trx) * d0, dy = (p.bty - try_) * d0, dz = d0, la = 0.0f, lb = 0.0f, lc = 0.0f,
@@ -1100,8 +1101,9 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
     // lanes, about in proportion to its tracks (a wavefront iterates until its
     // slowest vertex converges, so with equal groups the largest vertex would
     // set the pace): lk = floor(log2(c_k B / C)) for the team's B lanes and C
-    // tracks in all, then the vertex with the most tracks per lane doubles its
-    // lanes while the budget allows.  The blocks are placed largest first, so
+    // tracks in all (at least one; if those minimums overrun the budget, the
+    // blocks that lose least are halved until they fit), then the vertex with
+    // the most tracks per lane doubles its lanes while the budget allows.  The blocks are placed largest first, so
     // each is aligned to its size, as the group sums need.  Fewer vertices,
     // where the balancing costs more than it saves, and more than 64 keep L
     // lanes each.
@@ -1117,6 +1119,20 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 const int q = (lane < nl) ? max(1, (c * budget) / C) : 1;
                 int lp = min(6, 31 - __clz(q));
                 int tot = __shfl(wave_incl_scan((lane < nl) ? (1 << lp) : 0, lane), 63);
+                // many small vertices beside a large one take more than the
+                // budget at one lane each: halve the block that loses least
+                // (fewest tracks per lane after halving) until they fit
+                for (int it = 0; it < 64 && tot > budget; ++it) {
+                    const int r = (lane < nl && lp > 0) ? ((c + (1 << (lp - 1)) - 1) >> (lp - 1)) : 0x7FFFFF;
+                    const int key = wave_min((r << 8) | lane);
+                    if ((key >> 8) == 0x7FFFFF)
+                        break;
+                    const int kb = key & 0xFF;
+                    const int lb = __shfl(lp, kb);
+                    if (lane == kb)
+                        --lp;
+                    tot -= 1 << (lb - 1);
+                }
                 if (tot <= budget) {
                     fits = true;
                     for (int it = 0; it < 64; ++it) {

@@ -38,10 +38,14 @@ struct Request {
 enum class SlotState { Free, Open, Sealed, InFlight };
 
 // Each slot keeps its buffers in a few contiguous blocks so that a batch
-// moves with five copies: the eight track columns (one 2-D copy of rows of
+// moves with six copies: the eight track columns (one 2-D copy of rows of
 // cap_tracks floats), offsets and event count, vertex counts and status (one
-// 2-D copy), vertex records, and per-track vertex ids and weights (one 2-D
-// copy).
+// 2-D copy), per-event offsets of the written vertex records, the records
+// themselves (gathered into one dense array on the device, at most
+// kDenseBudget per event in this copy), and per-track vertex ids and weights
+// (one 2-D copy).  A batch with more records than that budget fetches the
+// rest when it completes.
+constexpr int kDenseBudget = 16;
 struct Slot {
     int id = 0;
     hipStream_t stream = nullptr;
@@ -57,11 +61,14 @@ struct Slot {
     int32_t *d_tout = nullptr;      // vertex ids, then weights: 2 rows of cap_tracks
     int32_t *d_tv = nullptr;
     float *d_tw = nullptr;
+    pv_vertex *d_dense = nullptr;   // written vertex records, event after event
+    int32_t *d_first = nullptr;     // cap_events + 1: offsets of each event's records, then the total
     // pinned host, same layouts
     float *h_in = nullptr;
     float *h_trk[8] = {};
     int32_t *h_offsets = nullptr;
-    pv_vertex *h_vtx = nullptr;
+    pv_vertex *h_vtx = nullptr;     // the dense records
+    int32_t *h_first = nullptr;
     int32_t *h_ns = nullptr, *h_nv = nullptr, *h_status = nullptr;
     int32_t *h_tout = nullptr, *h_tv = nullptr;
     float *h_tw = nullptr;
@@ -69,6 +76,7 @@ struct Slot {
     hipGraphExec_t graph = nullptr;
     hipEvent_t done = nullptr;
     int n_events = 0, n_tracks = 0;
+    int dense_copied = 0;           // records the batch's copy-back brought
     int64_t t_oldest = 0;
     std::vector<Request> reqs;
 };
@@ -101,10 +109,11 @@ namespace {
 
 void free_slot(Slot &s)
 {
-    for (void *p : {(void *)s.d_in, (void *)s.d_vtx, (void *)s.d_ns, (void *)s.d_tout, (void *)s.wq})
+    for (void *p : {(void *)s.d_in, (void *)s.d_vtx, (void *)s.d_ns, (void *)s.d_tout, (void *)s.wq,
+                    (void *)s.d_dense, (void *)s.d_first})
         if (p)
             (void)hipFree(p);
-    for (void *p : {(void *)s.h_in, (void *)s.h_vtx, (void *)s.h_ns, (void *)s.h_tout})
+    for (void *p : {(void *)s.h_in, (void *)s.h_vtx, (void *)s.h_ns, (void *)s.h_tout, (void *)s.h_first})
         if (p)
             (void)hipHostFree(p);
     if (s.graph)
@@ -119,7 +128,8 @@ size_t slot_device_bytes(const pv_server_config &c, const pv_params &p)
     const size_t T = (size_t)c.max_tracks_per_batch, E = (size_t)c.max_events_per_batch;
     return T * 8 * sizeof(float) + (E + 1) * sizeof(int32_t) + sizeof(int32_t) +
            E * (size_t)p.max_vertices_per_event * sizeof(pv_vertex) + 2 * E * sizeof(int32_t) +
-           T * (sizeof(int32_t) + sizeof(float)) + sizeof(pvk::WorkQueue) + 2 * E * sizeof(int32_t);
+           T * (sizeof(int32_t) + sizeof(float)) + sizeof(pvk::WorkQueue) + 2 * E * sizeof(int32_t) +
+           E * (size_t)p.max_vertices_per_event * sizeof(pv_vertex) + (E + 1) * sizeof(int32_t);
 }
 
 template <typename T>
@@ -178,6 +188,12 @@ int init_slot(pv_server &s, Slot &sl)
     if (rc == PV_OK)
         rc = host_alloc(&sl.h_ns, 2 * (size_t)E);
     if (rc == PV_OK)
+        rc = dev_alloc(&sl.d_dense, (size_t)E * mv);
+    if (rc == PV_OK)
+        rc = dev_alloc(&sl.d_first, (size_t)E + 1);
+    if (rc == PV_OK)
+        rc = host_alloc(&sl.h_first, (size_t)E + 1);
+    if (rc == PV_OK)
         rc = dev_alloc(&sl.d_tout, 2 * (size_t)T);
     if (rc == PV_OK)
         rc = host_alloc(&sl.h_tout, 2 * (size_t)T);
@@ -218,7 +234,9 @@ int init_slot(pv_server &s, Slot &sl)
     err = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess)
         return pvk::set_error(PV_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(err));
-    const int lerr = pvk::launch_batch(A, s.sched, false, sl.stream, nullptr);
+    int lerr = pvk::launch_batch(A, s.sched, false, sl.stream, nullptr);
+    if (lerr == (int)hipSuccess)
+        lerr = pvk::launch_compact(sl.d_vtx, sl.d_nv, sl.d_nev, E, mv, sl.d_dense, sl.d_first, sl.stream);
     hipGraph_t g = nullptr;
     err = hipStreamEndCapture(sl.stream, &g);
     if (lerr != (int)hipSuccess || err != hipSuccess) {
@@ -255,7 +273,10 @@ int dispatch(pv_server &s, Slot &sl)
             return pvk::set_error(PV_EHIP, "hipGraphLaunch: %s", hipGetErrorString(err));
     } else {
         const pvk::KArgs A = slot_args(s, sl, sl.wq, E);
-        const int lerr = pvk::launch_batch(A, s.sched, false, st, nullptr);
+        int lerr = pvk::launch_batch(A, s.sched, false, st, nullptr);
+        if (lerr == (int)hipSuccess)
+            lerr = pvk::launch_compact(sl.d_vtx, sl.d_nv, nullptr, E, s.params.max_vertices_per_event, sl.d_dense,
+                                       sl.d_first, st);
         if (lerr != (int)hipSuccess)
             return pvk::set_error(PV_EHIP, "server launch: %s", hipGetErrorString((hipError_t)lerr));
     }
@@ -264,7 +285,13 @@ int dispatch(pv_server &s, Slot &sl)
     err = hipMemcpy2DAsync(sl.h_ns, capE * sizeof(int32_t), sl.d_ns, capE * sizeof(int32_t),
                            (size_t)E * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_vtx, sl.d_vtx, sizeof(pv_vertex) * mv * (size_t)E, hipMemcpyDeviceToHost, st);
+        err = hipMemcpyAsync(sl.h_first, sl.d_first, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyDeviceToHost, st);
+    // the dense records, up to the budget (a batch averages about 10 per event
+    // on the served mix; more are fetched on completion)
+    sl.dense_copied = (int)std::min<size_t>(mv * (size_t)E, (size_t)kDenseBudget * (size_t)E);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(sl.h_vtx, sl.d_dense, sizeof(pv_vertex) * (size_t)sl.dense_copied,
+                             hipMemcpyDeviceToHost, st);
     if (err == hipSuccess && T > 0)   // vertex ids and weights: 2 rows of T at a pitch of capT
         err = hipMemcpy2DAsync(sl.h_tout, capT * sizeof(int32_t), sl.d_tout, capT * sizeof(int32_t),
                                (size_t)T * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
@@ -276,14 +303,25 @@ int dispatch(pv_server &s, Slot &sl)
 }
 
 // Scatter a finished slot's results into the callers' buffers.
-void complete(pv_server &s, Slot &sl, std::vector<pv_completion> &out)
+int complete(pv_server &s, Slot &sl, std::vector<pv_completion> &out)
 {
-    const size_t mv = (size_t)s.params.max_vertices_per_event;
+    const int total = sl.h_first[sl.n_events];
+    int rc = PV_OK;
+    if (total > sl.dense_copied) {
+        // more records than the budget: fetch the rest (not under the lock)
+        const size_t rest = (size_t)(total - sl.dense_copied);
+        hipError_t err = hipMemcpyAsync(sl.h_vtx + sl.dense_copied, sl.d_dense + sl.dense_copied,
+                                        sizeof(pv_vertex) * rest, hipMemcpyDeviceToHost, sl.stream);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(sl.stream);
+        if (err != hipSuccess)
+            rc = pvk::set_error(PV_EHIP, "server copy-out: %s", hipGetErrorString(err));
+    }
     for (int e = 0; e < sl.n_events; ++e) {
         const Request &r = sl.reqs[e];
         const int nv = sl.h_nv[e];
-        if (nv > 0 && r.vertices)
-            std::memcpy(r.vertices, sl.h_vtx + (size_t)e * mv, sizeof(pv_vertex) * (size_t)nv);
+        if (nv > 0 && r.vertices && rc == PV_OK)
+            std::memcpy(r.vertices, sl.h_vtx + sl.h_first[e], sizeof(pv_vertex) * (size_t)nv);
         if (r.n_tracks > 0) {
             std::memcpy(r.track_vertex, sl.h_tv + r.first_track, sizeof(int32_t) * (size_t)r.n_tracks);
             std::memcpy(r.track_weight, sl.h_tw + r.first_track, sizeof(float) * (size_t)r.n_tracks);
@@ -296,6 +334,7 @@ void complete(pv_server &s, Slot &sl, std::vector<pv_completion> &out)
         c.t_done_ns = now_ns();
         out.push_back(c);
     }
+    return rc;
 }
 
 void seal_open(pv_server &s)
@@ -340,9 +379,15 @@ void worker_main(pv_server *sp)
                 finished.push_back(id);
             }
             done.clear();
-            for (int id : finished)
-                complete(s, s.slots[id], done);
+            int crc = PV_OK;
+            for (int id : finished) {
+                const int rc = complete(s, s.slots[id], done);
+                if (rc != PV_OK)
+                    crc = rc;
+            }
             lk.lock();
+            if (crc != PV_OK && s.worker_error == PV_OK)
+                s.worker_error = crc;
             for (const auto &c : done)
                 s.completed.push_back(c);
             s.n_completed += (int64_t)done.size();

@@ -344,6 +344,31 @@ def test_config4_high_pileup_full_size_autotuned():
     _check_full_size_autotuned("pp_mu40_20kev", "mu=40 20k events")
 
 
+@pytest.mark.parametrize("waves", [1, 2])
+def test_fit_lane_map_one_dominant_vertex_among_many_small(waves):
+    """More than 8 vertices share a team's lanes in proportion to their
+    tracks: one 600-track vertex beside 40 vertices of 4 tracks.  At one lane
+    per small vertex the minimums overrun a one-wavefront team's 64 lanes, so
+    the large vertex's block is halved until they fit; two wavefronts hold
+    them without halving.  Capacity 1024, so the team keeps the event."""
+    rng = np.random.default_rng(47)
+    ev = np.concatenate([_exact_event((0.0, 0.0, 150.0), 600, rng)] +
+                        [_exact_event((0.0, 0.0, -120.0 + 6.0 * k), 4, rng) for k in range(40)])
+    b = synth.concat([synth.from_tracks([ev, ev[::-1].copy()]), synth.generate("pp_mu5_100ev", n_events=6)])
+    sched = dict(waves_per_team=waves, track_capacity=1024, persistent=4, teams_per_cu=0)
+    g, o, _ = check(b, schedule=sched, name=f"dominant vertex, W={waves}")
+    assert int(o.n_vertices[0]) == 41 and int(g.n_vertices[0]) == 41
+
+
+@pytest.mark.parametrize("cap", [1024, 2048])
+def test_config4_high_pileup_one_wavefront_teams(cap):
+    """High pile-up on one-wavefront teams: the proportional lane map with a
+    64-lane budget."""
+    b = synth.generate("pp_mu40_20kev", n_events=300, keep_truth=False)
+    check(b, schedule=dict(waves_per_team=1, track_capacity=cap, persistent=4, teams_per_cu=0), debug=True,
+          name=f"mu=40 300 events, one wavefront, capacity {cap}")
+
+
 @pytest.mark.parametrize("cap", [1536, 2048])
 def test_config4_high_pileup_large_teams(cap):
     """High pile-up under the schedules that suit it: four-wavefront teams

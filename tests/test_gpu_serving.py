@@ -84,6 +84,32 @@ def test_served_mix_equals_batched_and_oracle(graphs, persistent):
     assert rep.ok(), "\n".join(rep.problems)
 
 
+def test_served_mix_20k_events_against_the_oracle():
+    """20,000 events of the served mix (mu log-uniform in [1, 40]) through the
+    continuous-batching server at a Poisson rate near its capacity, in the
+    benchmark's server configuration: every result against the oracle."""
+    batch = synth.generate_parallel("served_mulog_200kev", n_events=20000, workers=8)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=1024, max_tracks_per_batch=1024 * 600, n_slots=6,
+                                      n_streams=3, max_wait_us=100, use_graphs=1)
+    say(f"served 20k: {batch.n_events} events, {batch.n_tracks} tracks")
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, poisson_offsets(batch.n_events, 8.0e5, seed=5))
+        st = srv.stats()
+    say(f"served 20k: stats {st}")
+    assert st["completed"] == batch.n_events and st["batches"] > 1
+    order = np.argsort(comp["tag"])
+    assert np.array_equal(comp["tag"][order], np.arange(batch.n_events))
+    o = oracle.find(batch, parity.oracle_params(params))
+    g = pv.HostResult(n_vertices=comp["n_vertices"][order].astype(np.int32),
+                      status=comp["status"][order].astype(np.int32), vertices=host.vertices[:batch.n_events],
+                      track_vertex=host.track_vertex[:batch.n_tracks], track_weight=host.track_weight[:batch.n_tracks])
+    rep = parity.compare(batch, g, o)
+    say(f"served 20k vs oracle: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+
+
 def test_event_alone_equals_event_in_mix():
     batch = synth.generate("served_mulog_200kev", n_events=400, keep_truth=False)
     params = pv.make_params({"max_vertices_per_event": 96})
