@@ -56,6 +56,9 @@ extern "C" {
                                      the first ones in z were kept                      */
 #define PV_EV_OFFSETS_INVALID  8  /* offsets of this event out of order or range;
                                      event skipped, its track outputs left untouched    */
+#define PV_EV_FIT_FAILED      16  /* a candidate's fit failed and the candidate was
+                                     dropped: no track kept weight, or the normal
+                                     matrix of the Newton step (Eq. 15) was singular    */
 
 /* per-vertex flag bits */
 #define PV_VX_NOT_CONVERGED    1  /* stopped at max_iter (Sec. 3.5 caps the iterations) */

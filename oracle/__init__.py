@@ -23,6 +23,7 @@ _LIB = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle.so")
 
 TR_HIST, TR_ASSOC, TR_NONFINITE = 1, 2, 4
 EV_NONFINITE_INPUT, EV_TOO_MANY_TRACKS, EV_VERTEX_OVERFLOW, EV_OFFSETS_INVALID = 1, 2, 4, 8
+EV_FIT_FAILED = 16
 VX_NOT_CONVERGED = 1
 
 

@@ -856,6 +856,8 @@ static void mv_event(const float *const ev[8], int n, const float beam[4], const
         const double xs = (double)beam[0] + (double)beam[2] * zs;
         const double ys = (double)beam[1] + (double)beam[3] * zs;
         ok[j] = !fit_core(ev, idx, oth, m, xs, ys, zs, p, forced_iters(p, cl[j].peak), &cand[j], w);
+        if (!ok[j])
+            *status |= ORC_EV_FIT_FAILED;
         int cnt = 0, near = 0;
         for (k = 0; k < m; ++k) {
             wall[(size_t)j * nn + idx[k]] = w[k];
@@ -1045,6 +1047,8 @@ static void find_event(const float *const trk[8], int a, int n, const float beam
         const double ys = (double)beam[1] + (double)beam[3] * zs;
         orc_vertex v;
         const int bad = fit_core(ev, idx, NULL, m, xs, ys, zs, p, forced_iters(p, cl[q].peak), &v, w);
+        if (bad)
+            *status |= ORC_EV_FIT_FAILED;
         const int gas = cl[q].peak < gas_bin;
         int keep = !bad && cl[q].n_assoc >= (gas ? p->pv_min_gas : p->pv_min_pp);
         if (keep && !gas) {

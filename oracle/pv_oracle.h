@@ -33,6 +33,8 @@ extern "C" {
 #define ORC_EV_TOO_MANY_TRACKS  2
 #define ORC_EV_VERTEX_OVERFLOW  4
 #define ORC_EV_OFFSETS_INVALID  8
+#define ORC_EV_FIT_FAILED      16   /* a candidate's fit failed (no weight left, or a
+                                       singular normal matrix) and it was dropped */
 
 /* Per-vertex flag bits. */
 #define ORC_VX_NOT_CONVERGED    1

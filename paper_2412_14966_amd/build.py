@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpvfind.so")
 SOURCES = [os.path.join(CSRC, "pvfind_kernels.hip"), os.path.join(CSRC, "pvfind_api.cpp"),
-           os.path.join(CSRC, "pvfind_server.cpp"), os.path.join(CSRC, "pvfind_measure.hip"),
+           os.path.join(CSRC, "pvfind_params.cpp"), os.path.join(CSRC, "pvfind_server.cpp"),
+           os.path.join(CSRC, "pvfind_server_hip.cpp"), os.path.join(CSRC, "pvfind_measure.hip"),
            os.path.join(CSRC, "pvfind_compact.hip")]
 ARCH = os.environ.get("PV_OFFLOAD_ARCH", "gfx950")
 

@@ -83,10 +83,20 @@ struct LaunchEvents {
     bool large = false;
 };
 
-// Host helpers shared by the C ABI files (pvfind_api.cpp).
+// Host helpers shared by the C ABI files (pvfind_params.cpp, which needs no
+// device, defines the first six).
+// Record the calling thread's error message (pv_last_error) and return code.
 int set_error(int code, const char *fmt, ...);
+// Validate params and beamline and derive the kernels' parameters.
 int derive_kparams(const pv_params *p, const pv_beamline *bl, KParams &k);
+// A requested schedule with its zero fields taken from the process default.
+pv_schedule resolve_schedule(const pv_schedule *requested);
+int validate_schedule(const pv_schedule &s);
+// resolve_schedule, then validate_schedule.
 int schedule_for(const pv_schedule *requested, pv_schedule &out);
+// Null and count checks of the find calls' arguments.
+int check_find_args(const pv_tracks *tracks, const int32_t *offsets, int32_t n_events, const pv_beamline *beamline,
+                    const pv_params *params, const pv_vertices_out *ov, const pv_track_out *ot);
 int workspace_for(void *stream, int n_events, WorkQueue **out, int32_t **order);
 
 // Device address of the order list of a workspace with `capacity` entries per list.

@@ -413,6 +413,8 @@ __device__ __forceinline__ void fit_vertices(Smem<W, CAP, BIG, MV> &S, const KPa
             S.vf.tx[k] = trx;
             S.vf.ty[k] = try_;
             S.vf.info[k] = nit | (conv ? 0 : kInfoNotConv) | (failed ? kInfoFailed : 0);
+            if (failed)
+                atomicOr(&S.status, PV_EV_FIT_FAILED);
         }
     }
 }

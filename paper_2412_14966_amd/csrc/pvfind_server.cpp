@@ -1,20 +1,20 @@
-// pvfind_server.cpp -- continuous-batching server on top of the pv_find
-// kernels: a pool of batch slots (pinned staging, device buffers, optional
-// hipGraph of the launches), admission by free slot, a worker thread that
-// seals, launches and completes batches on several streams.
-#include <hip/hip_runtime.h>
-
+// pvfind_server.cpp -- continuous-batching server on top of pv_find: a pool
+// of batch slots, admission by free slot, a worker thread that seals,
+// dispatches and completes batches on several streams.  The device side of a
+// slot (buffers, streams, graphs, launches) sits behind pvk::ServerDevice
+// (pvfind_server_hip.cpp); this file holds no device code.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
 
-#include "pvfind_internal.h"
+#include "pvfind_server_device.h"
 
 namespace {
 
@@ -37,46 +37,23 @@ struct Request {
 
 enum class SlotState { Free, Open, Sealed, InFlight };
 
-// Each slot keeps its buffers in a few contiguous blocks so that a batch
-// moves with six copies: the eight track columns (one 2-D copy of rows of
-// cap_tracks floats), offsets and event count, vertex counts and status (one
-// 2-D copy), per-event offsets of the written vertex records, the records
-// themselves (gathered into one dense array on the device, at most
-// kDenseBudget per event in this copy), and per-track vertex ids and weights
-// (one 2-D copy).  A batch with more records than that budget fetches the
-// rest when it completes.
-constexpr int kDenseBudget = 16;
+// The vertex records come back in a copy sized before their number is
+// known: kDenseBase per event plus one per kDenseTracks tracks, which holds a
+// batch's records with room to spare at every pile-up (about one vertex per
+// 25 tracks).  A batch with more records gets a second copy of the rest once
+// its counts are back, and completes when that copy has; the worker does not
+// wait for it.
+constexpr size_t kDenseBase = 2;
+constexpr size_t kDenseTracks = 16;
+
 struct Slot {
     int id = 0;
-    hipStream_t stream = nullptr;
     SlotState state = SlotState::Free;
-    // device
-    float *d_in = nullptr;          // 8 columns of cap_tracks floats, then cap_events + 2 ints
-    float *d_trk[8] = {};
-    int32_t *d_offsets = nullptr;   // cap_events + 1 offsets, then the event count
-    int32_t *d_nev = nullptr;
-    pv_vertex *d_vtx = nullptr;
-    int32_t *d_ns = nullptr;        // vertex counts, then status: 2 rows of cap_events
-    int32_t *d_nv = nullptr, *d_status = nullptr;
-    int32_t *d_tout = nullptr;      // vertex ids, then weights: 2 rows of cap_tracks
-    int32_t *d_tv = nullptr;
-    float *d_tw = nullptr;
-    pv_vertex *d_dense = nullptr;   // written vertex records, event after event
-    int32_t *d_first = nullptr;     // cap_events + 1: offsets of each event's records, then the total
-    // pinned host, same layouts
-    float *h_in = nullptr;
-    float *h_trk[8] = {};
-    int32_t *h_offsets = nullptr;
-    pv_vertex *h_vtx = nullptr;     // the dense records
-    int32_t *h_first = nullptr;
-    int32_t *h_ns = nullptr, *h_nv = nullptr, *h_status = nullptr;
-    int32_t *h_tout = nullptr, *h_tv = nullptr;
-    float *h_tw = nullptr;
-    pvk::WorkQueue *wq = nullptr;   // this slot's own queue counters (baked into its graph)
-    hipGraphExec_t graph = nullptr;
-    hipEvent_t done = nullptr;
+    pvk::SlotHost h;
     int n_events = 0, n_tracks = 0;
-    int dense_copied = 0;           // records the batch's copy-back brought
+    int dense_copied = 0;           // records the batch's first copy-back brings
+    bool rest_issued = false;       // the second copy (records past dense_copied) was started
+    int rest_rc = PV_OK;            // its start status
     int64_t t_oldest = 0;
     std::vector<Request> reqs;
 };
@@ -84,13 +61,12 @@ struct Slot {
 }  // namespace
 
 struct pv_server {
-    int device = 0;
     pv_params params{};
     pv_beamline beamline{};
     pv_server_config cfg{};
     pv_schedule sched{};
     pvk::KParams kp{};
-    std::vector<hipStream_t> streams;
+    std::unique_ptr<pvk::ServerDevice> dev;
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -105,236 +81,84 @@ struct pv_server {
     int worker_error = PV_OK;
 };
 
-namespace {
+namespace pvk {
 
-void free_slot(Slot &s)
-{
-    for (void *p : {(void *)s.d_in, (void *)s.d_vtx, (void *)s.d_ns, (void *)s.d_tout, (void *)s.wq,
-                    (void *)s.d_dense, (void *)s.d_first})
-        if (p)
-            (void)hipFree(p);
-    for (void *p : {(void *)s.h_in, (void *)s.h_vtx, (void *)s.h_ns, (void *)s.h_tout, (void *)s.h_first})
-        if (p)
-            (void)hipHostFree(p);
-    if (s.graph)
-        (void)hipGraphExecDestroy(s.graph);
-    if (s.done)
-        (void)hipEventDestroy(s.done);
-    s = Slot();
-}
-
-size_t slot_device_bytes(const pv_server_config &c, const pv_params &p)
+size_t server_slot_bytes(const pv_server_config &c, const pv_params &p)
 {
     const size_t T = (size_t)c.max_tracks_per_batch, E = (size_t)c.max_events_per_batch;
-    return T * 8 * sizeof(float) + (E + 1) * sizeof(int32_t) + sizeof(int32_t) +
-           E * (size_t)p.max_vertices_per_event * sizeof(pv_vertex) + 2 * E * sizeof(int32_t) +
-           T * (sizeof(int32_t) + sizeof(float)) + sizeof(pvk::WorkQueue) + 2 * E * sizeof(int32_t) +
-           E * (size_t)p.max_vertices_per_event * sizeof(pv_vertex) + (E + 1) * sizeof(int32_t);
+    const size_t mv = (size_t)p.max_vertices_per_event;
+    return T * 8 * sizeof(float) + (E + 2) * sizeof(int32_t)       // track columns, offsets, event count
+           + E * mv * sizeof(pv_vertex) + 2 * E * sizeof(int32_t)  // vertex slots, counts and status
+           + T * (sizeof(int32_t) + sizeof(float))                 // per-track outputs
+           + sizeof(WorkQueue) + 2 * E * sizeof(int32_t)           // work queue: deferred list, order
+           + E * mv * sizeof(pv_vertex) + (E + 1) * sizeof(int32_t);   // dense records, their offsets
 }
 
-template <typename T>
-int dev_alloc(T **p, size_t n)
-{
-    const hipError_t err = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
-    return err == hipSuccess ? PV_OK : pvk::set_error(PV_ENOMEM, "hipMalloc: %s", hipGetErrorString(err));
-}
+}  // namespace pvk
 
-template <typename T>
-int host_alloc(T **p, size_t n)
-{
-    const hipError_t err = hipHostMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault);
-    return err == hipSuccess ? PV_OK : pvk::set_error(PV_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(err));
-}
+namespace {
 
-pvk::KArgs slot_args(const pv_server &s, const Slot &sl, pvk::WorkQueue *wq, int n_events)
-{
-    pvk::KArgs A;
-    std::memset(&A, 0, sizeof(A));
-    A.x = sl.d_trk[0];
-    A.y = sl.d_trk[1];
-    A.z = sl.d_trk[2];
-    A.tx = sl.d_trk[3];
-    A.ty = sl.d_trk[4];
-    A.cxx = sl.d_trk[5];
-    A.cxtx = sl.d_trk[6];
-    A.ctxtx = sl.d_trk[7];
-    A.offsets = sl.d_offsets;
-    A.n_events = n_events;
-    A.vout = sl.d_vtx;
-    A.nv_out = sl.d_nv;
-    A.status_out = sl.d_status;
-    A.trk_vtx = sl.d_tv;
-    A.trk_w = sl.d_tw;
-    A.wq = wq;
-    A.order = (s.sched.persistent >= 3) ? pvk::order_list(wq, s.cfg.max_events_per_batch) : nullptr;
-    A.p = s.kp;
-    return A;
-}
-
-int init_slot(pv_server &s, Slot &sl)
-{
-    const int T = s.cfg.max_tracks_per_batch, E = s.cfg.max_events_per_batch;
-    const int mv = s.params.max_vertices_per_event;
-    const size_t in_floats = 8 * (size_t)T + (size_t)E + 2;   // int32 and float are both 4 bytes
-    int rc = dev_alloc(&sl.d_in, in_floats);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_in, in_floats);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_vtx, (size_t)E * mv);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_vtx, (size_t)E * mv);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_ns, 2 * (size_t)E);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_ns, 2 * (size_t)E);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_dense, (size_t)E * mv);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_first, (size_t)E + 1);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_first, (size_t)E + 1);
-    if (rc == PV_OK)
-        rc = dev_alloc(&sl.d_tout, 2 * (size_t)T);
-    if (rc == PV_OK)
-        rc = host_alloc(&sl.h_tout, 2 * (size_t)T);
-    if (rc != PV_OK)
-        return rc;
-    for (int k = 0; k < 8; ++k) {
-        sl.d_trk[k] = sl.d_in + (size_t)k * T;
-        sl.h_trk[k] = sl.h_in + (size_t)k * T;
-    }
-    sl.d_offsets = reinterpret_cast<int32_t *>(sl.d_in + 8 * (size_t)T);
-    sl.h_offsets = reinterpret_cast<int32_t *>(sl.h_in + 8 * (size_t)T);
-    sl.d_nev = sl.d_offsets + E + 1;
-    sl.d_nv = sl.d_ns;
-    sl.d_status = sl.d_ns + E;
-    sl.h_nv = sl.h_ns;
-    sl.h_status = sl.h_ns + E;
-    sl.d_tv = sl.d_tout;
-    sl.d_tw = reinterpret_cast<float *>(sl.d_tout + T);
-    sl.h_tv = sl.h_tout;
-    sl.h_tw = reinterpret_cast<float *>(sl.h_tout + T);
-    const size_t wq_bytes = sizeof(pvk::WorkQueue) + 2 * sizeof(int32_t) * (size_t)E;   // deferred list, order
-    hipError_t err = hipMalloc((void **)&sl.wq, wq_bytes);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_ENOMEM, "hipMalloc: %s", hipGetErrorString(err));
-    err = hipMemset(sl.wq, 0, wq_bytes);
-    if (err == hipSuccess)
-        err = hipDeviceSynchronize();
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "workspace init: %s", hipGetErrorString(err));
-    err = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "hipEventCreate: %s", hipGetErrorString(err));
-    sl.reqs.reserve(E);
-    if (!s.cfg.use_graphs)
-        return PV_OK;
-    pvk::KArgs A = slot_args(s, sl, sl.wq, E);
-    A.n_events_dev = sl.d_nev;
-    err = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(err));
-    int lerr = pvk::launch_batch(A, s.sched, false, sl.stream, nullptr);
-    if (lerr == (int)hipSuccess)
-        lerr = pvk::launch_compact(sl.d_vtx, sl.d_nv, sl.d_nev, E, mv, sl.d_dense, sl.d_first, sl.stream);
-    hipGraph_t g = nullptr;
-    err = hipStreamEndCapture(sl.stream, &g);
-    if (lerr != (int)hipSuccess || err != hipSuccess) {
-        if (g)
-            (void)hipGraphDestroy(g);
-        return pvk::set_error(PV_EHIP, "graph capture: %s",
-                              hipGetErrorString(lerr != (int)hipSuccess ? (hipError_t)lerr : err));
-    }
-    err = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(err));
-    return PV_OK;
-}
-
-// Enqueue copies, launch and copy-back of a sealed slot on its stream.
+// Start a sealed slot's batch on the device.
 int dispatch(pv_server &s, Slot &sl)
 {
-    const int E = sl.n_events, T = sl.n_tracks;
-    const size_t capE = (size_t)s.cfg.max_events_per_batch, capT = (size_t)s.cfg.max_tracks_per_batch;
-    hipStream_t st = sl.stream;
-    sl.h_offsets[capE + 1] = E;
-    hipError_t err = hipSuccess;
-    if (T > 0)   // the eight columns: 8 rows of T floats at a pitch of capT floats
-        err = hipMemcpy2DAsync(sl.d_in, capT * sizeof(float), sl.h_in, capT * sizeof(float),
-                               (size_t)T * sizeof(float), 8, hipMemcpyHostToDevice, st);
-    if (err == hipSuccess)   // offsets and, at capE + 1, the event count
-        err = hipMemcpyAsync(sl.d_offsets, sl.h_offsets, sizeof(int32_t) * (capE + 2), hipMemcpyHostToDevice, st);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "server copy-in: %s", hipGetErrorString(err));
-    if (sl.graph) {
-        err = hipGraphLaunch(sl.graph, st);
-        if (err != hipSuccess)
-            return pvk::set_error(PV_EHIP, "hipGraphLaunch: %s", hipGetErrorString(err));
-    } else {
-        const pvk::KArgs A = slot_args(s, sl, sl.wq, E);
-        int lerr = pvk::launch_batch(A, s.sched, false, st, nullptr);
-        if (lerr == (int)hipSuccess)
-            lerr = pvk::launch_compact(sl.d_vtx, sl.d_nv, nullptr, E, s.params.max_vertices_per_event, sl.d_dense,
-                                       sl.d_first, st);
-        if (lerr != (int)hipSuccess)
-            return pvk::set_error(PV_EHIP, "server launch: %s", hipGetErrorString((hipError_t)lerr));
-    }
+    const size_t E = (size_t)sl.n_events, T = (size_t)sl.n_tracks;
     const size_t mv = (size_t)s.params.max_vertices_per_event;
-    // vertex counts and status: 2 rows of E ints at a pitch of capE
-    err = hipMemcpy2DAsync(sl.h_ns, capE * sizeof(int32_t), sl.d_ns, capE * sizeof(int32_t),
-                           (size_t)E * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_first, sl.d_first, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyDeviceToHost, st);
-    // the dense records, up to the budget (a batch averages about 10 per event
-    // on the served mix; more are fetched on completion)
-    sl.dense_copied = (int)std::min<size_t>(mv * (size_t)E, (size_t)kDenseBudget * (size_t)E);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(sl.h_vtx, sl.d_dense, sizeof(pv_vertex) * (size_t)sl.dense_copied,
-                             hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess && T > 0)   // vertex ids and weights: 2 rows of T at a pitch of capT
-        err = hipMemcpy2DAsync(sl.h_tout, capT * sizeof(int32_t), sl.d_tout, capT * sizeof(int32_t),
-                               (size_t)T * sizeof(int32_t), 2, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess)
-        err = hipEventRecord(sl.done, st);
-    if (err != hipSuccess)
-        return pvk::set_error(PV_EHIP, "server copy-out: %s", hipGetErrorString(err));
-    return PV_OK;
+    sl.dense_copied = (int)std::min(mv * E, kDenseBase * E + T / kDenseTracks);
+    sl.rest_issued = false;
+    sl.rest_rc = PV_OK;
+    return s.dev->dispatch(sl.id, sl.n_events, sl.n_tracks, sl.dense_copied);
+}
+
+// Second copy-back of a finished batch: the records past the first copy.
+// Returns true when the batch must wait for it.
+bool fetch_rest(pv_server &s, Slot &sl)
+{
+    if (sl.rest_issued)
+        return false;
+    const int total = sl.h.first[sl.n_events];
+    if (total <= sl.dense_copied)
+        return false;
+    sl.rest_issued = true;
+    const int rc = s.dev->fetch(sl.id, sl.dense_copied, total - sl.dense_copied);
+    if (rc != PV_OK) {
+        sl.rest_rc = rc;
+        return false;
+    }
+    return true;
 }
 
 // Scatter a finished slot's results into the callers' buffers.
-int complete(pv_server &s, Slot &sl, std::vector<pv_completion> &out)
+int complete(Slot &sl, std::vector<pv_completion> &out)
 {
-    const int total = sl.h_first[sl.n_events];
-    int rc = PV_OK;
-    if (total > sl.dense_copied) {
-        // more records than the budget: fetch the rest (not under the lock)
-        const size_t rest = (size_t)(total - sl.dense_copied);
-        hipError_t err = hipMemcpyAsync(sl.h_vtx + sl.dense_copied, sl.d_dense + sl.dense_copied,
-                                        sizeof(pv_vertex) * rest, hipMemcpyDeviceToHost, sl.stream);
-        if (err == hipSuccess)
-            err = hipStreamSynchronize(sl.stream);
-        if (err != hipSuccess)
-            rc = pvk::set_error(PV_EHIP, "server copy-out: %s", hipGetErrorString(err));
-    }
+    const int total = sl.h.first[sl.n_events];
+    int rc = sl.rest_rc;
+    if (rc == PV_OK && total > sl.dense_copied && !sl.rest_issued)
+        rc = pvk::set_error(PV_EHIP, "server: vertex records past the first copy were not fetched");
     for (int e = 0; e < sl.n_events; ++e) {
         const Request &r = sl.reqs[e];
-        const int nv = sl.h_nv[e];
+        const int nv = sl.h.nv[e];
         if (nv > 0 && r.vertices && rc == PV_OK)
-            std::memcpy(r.vertices, sl.h_vtx + sl.h_first[e], sizeof(pv_vertex) * (size_t)nv);
+            std::memcpy(r.vertices, sl.h.vtx + sl.h.first[e], sizeof(pv_vertex) * (size_t)nv);
         if (r.n_tracks > 0) {
-            std::memcpy(r.track_vertex, sl.h_tv + r.first_track, sizeof(int32_t) * (size_t)r.n_tracks);
-            std::memcpy(r.track_weight, sl.h_tw + r.first_track, sizeof(float) * (size_t)r.n_tracks);
+            std::memcpy(r.track_vertex, sl.h.tv + r.first_track, sizeof(int32_t) * (size_t)r.n_tracks);
+            std::memcpy(r.track_weight, sl.h.tw + r.first_track, sizeof(float) * (size_t)r.n_tracks);
         }
         pv_completion c;
         c.tag = r.tag;
-        c.status = sl.h_status[e];
+        c.status = sl.h.status[e];
         c.n_vertices = nv;
         c.t_arrival_ns = r.t_arrival;
         c.t_done_ns = now_ns();
         out.push_back(c);
     }
     return rc;
+}
+
+void release(Slot &sl)
+{
+    sl.state = SlotState::Free;
+    sl.n_events = sl.n_tracks = 0;
+    sl.reqs.clear();
 }
 
 void seal_open(pv_server &s)
@@ -351,38 +175,36 @@ void seal_open(pv_server &s)
 void worker_main(pv_server *sp)
 {
     pv_server &s = *sp;
-    (void)hipSetDevice(s.device);
+    s.dev->bind_thread();
     std::vector<pv_completion> done;
     std::vector<int> finished;
     // s.inflight is only touched by this thread; the lock guards the slot
     // states, the open / sealed queues and the completion list, which the
-    // callers share.  No HIP call is made with the lock held.
+    // callers share.  No device call is made with the lock held.
     std::unique_lock<std::mutex> lk(s.mu);
     while (!s.stop) {
         // completions
         if (!s.inflight.empty()) {
             lk.unlock();
             finished.clear();
+            int qrc = PV_OK;
             for (size_t i = 0; i < s.inflight.size();) {
                 const int id = s.inflight[i];
-                const hipError_t q = hipEventQuery(s.slots[id].done);
-                if (q == hipErrorNotReady) {
+                const int q = s.dev->query(id);
+                if (q == 1 || (q == PV_OK && fetch_rest(s, s.slots[id]))) {
                     ++i;
                     continue;
                 }
-                if (q != hipSuccess) {
-                    std::lock_guard<std::mutex> g(s.mu);
-                    if (s.worker_error == PV_OK)
-                        s.worker_error = pvk::set_error(PV_EHIP, "server batch: %s", hipGetErrorString(q));
-                }
+                if (q != PV_OK && qrc == PV_OK)
+                    qrc = q;
                 s.inflight.erase(s.inflight.begin() + (long)i);
                 finished.push_back(id);
             }
             done.clear();
-            int crc = PV_OK;
+            int crc = qrc;
             for (int id : finished) {
-                const int rc = complete(s, s.slots[id], done);
-                if (rc != PV_OK)
+                const int rc = complete(s.slots[id], done);
+                if (rc != PV_OK && crc == PV_OK)
                     crc = rc;
             }
             lk.lock();
@@ -391,19 +213,15 @@ void worker_main(pv_server *sp)
             for (const auto &c : done)
                 s.completed.push_back(c);
             s.n_completed += (int64_t)done.size();
-            for (int id : finished) {
-                Slot &sl = s.slots[id];
-                sl.state = SlotState::Free;
-                sl.n_events = sl.n_tracks = 0;
-                sl.reqs.clear();
-            }
+            for (int id : finished)
+                release(s.slots[id]);
             if (!finished.empty())
                 s.cv_done.notify_all();
         }
         // continuous batching: a batch is sealed when it is full, or when a
-        // stream is free and either the GPU is idle or its oldest event has
-        // waited max_wait_us.  While every stream is busy the open batch keeps
-        // growing, so batches grow with the load.
+        // stream is free and either the device is idle or its oldest event
+        // has waited max_wait_us.  While every stream is busy the open batch
+        // keeps growing, so batches grow with the load.
         if (s.open >= 0) {
             const Slot &o = s.slots[s.open];
             const int busy = (int)(s.inflight.size() + s.sealed.size());
@@ -413,7 +231,8 @@ void worker_main(pv_server *sp)
             if (o.n_events > 0 && (o.n_events >= s.cfg.max_events_per_batch || (stream_free && (idle || waited))))
                 seal_open(s);
         }
-        // launches, oldest batch first, without the lock
+        // dispatch, oldest batch first, without the lock; a batch the device
+        // refuses is dropped and its error reported by every later call
         while (!s.sealed.empty() && (int)s.inflight.size() < s.cfg.n_streams) {
             const int id = s.sealed.front();
             s.sealed.pop_front();
@@ -424,9 +243,14 @@ void worker_main(pv_server *sp)
             lk.unlock();
             const int rc = dispatch(s, sl);
             lk.lock();
-            if (rc != PV_OK && s.worker_error == PV_OK)
-                s.worker_error = rc;
-            s.inflight.push_back(id);
+            if (rc != PV_OK) {
+                if (s.worker_error == PV_OK)
+                    s.worker_error = rc;
+                release(sl);
+                s.cv_done.notify_all();
+            } else {
+                s.inflight.push_back(id);
+            }
         }
         if (s.inflight.empty() && s.sealed.empty() && (s.open < 0 || s.slots[s.open].n_events == 0)) {
             s.cv_work.wait_for(lk, std::chrono::milliseconds(5));
@@ -472,45 +296,31 @@ int pv_server_create(pv_server **out, const pv_params *params, const pv_beamline
         return pvk::set_error(PV_EINVAL, "server: bad configuration");
     if (c.max_tracks_per_batch < params->max_tracks_per_event && c.max_events_per_batch == 1)
         return pvk::set_error(PV_EINVAL, "server: a single-event slot must hold max_tracks_per_event tracks");
-    auto s = new pv_server();
+    std::unique_ptr<pv_server> s(new pv_server());
     s->params = *params;
     s->beamline = *beamline;
     s->cfg = c;
     int rc = pvk::derive_kparams(params, beamline, s->kp);
     if (rc == PV_OK)
         rc = pvk::schedule_for(schedule, s->sched);
-    const size_t per_slot = slot_device_bytes(c, *params);
-    if (rc == PV_OK && (double)per_slot * c.n_slots > (double)c.device_budget_bytes)
-        rc = pvk::set_error(PV_EINVAL, "server: %d slots of %zu bytes exceed the device budget of %lld bytes",
-                            c.n_slots, per_slot, (long long)c.device_budget_bytes);
-    if (rc == PV_OK && hipGetDevice(&s->device) != hipSuccess)
-        rc = pvk::set_error(PV_EHIP, "hipGetDevice failed");
-    for (int k = 0; k < c.n_streams && rc == PV_OK; ++k) {
-        hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
-            rc = pvk::set_error(PV_EHIP, "hipStreamCreate failed");
-        else
-            s->streams.push_back(st);
-    }
-    if (rc == PV_OK) {
-        s->slots.resize((size_t)c.n_slots);
-        for (int k = 0; k < c.n_slots && rc == PV_OK; ++k) {
-            s->slots[k].id = k;
-            s->slots[k].stream = s->streams[(size_t)(k % c.n_streams)];
-            rc = init_slot(*s, s->slots[k]);
-        }
-        s->device_bytes = (int64_t)per_slot * c.n_slots;
-    }
-    if (rc != PV_OK) {
-        for (auto &sl : s->slots)
-            free_slot(sl);
-        for (auto st : s->streams)
-            (void)hipStreamDestroy(st);
-        delete s;
+    if (rc != PV_OK)
         return rc;
+    const size_t per_slot = pvk::server_slot_bytes(c, *params);
+    if ((double)per_slot * c.n_slots > (double)c.device_budget_bytes)
+        return pvk::set_error(PV_EINVAL, "server: %d slots of %zu bytes exceed the device budget of %lld bytes",
+                              c.n_slots, per_slot, (long long)c.device_budget_bytes);
+    rc = pvk::make_server_device(c, *params, s->kp, s->sched, &s->dev);
+    if (rc != PV_OK)
+        return rc;
+    s->slots.resize((size_t)c.n_slots);
+    for (int k = 0; k < c.n_slots; ++k) {
+        s->slots[k].id = k;
+        s->slots[k].h = s->dev->host(k);
+        s->slots[k].reqs.reserve((size_t)c.max_events_per_batch);
     }
-    s->worker = std::thread(worker_main, s);
-    *out = s;
+    s->device_bytes = s->dev->device_bytes();
+    s->worker = std::thread(worker_main, s.get());
+    *out = s.release();
     return PV_OK;
 }
 
@@ -543,7 +353,7 @@ int pv_server_submit(pv_server *s, const pv_request *req, uint64_t tag, int64_t 
             if (sl.state == SlotState::Free) {
                 sl.state = SlotState::Open;
                 sl.n_events = sl.n_tracks = 0;
-                sl.h_offsets[0] = 0;
+                sl.h.offsets[0] = 0;
                 s->open = sl.id;
                 break;
             }
@@ -554,7 +364,7 @@ int pv_server_submit(pv_server *s, const pv_request *req, uint64_t tag, int64_t 
     }
     Slot &sl = s->slots[s->open];
     for (int k = 0; k < 8 && n > 0; ++k)
-        std::memcpy(sl.h_trk[k] + sl.n_tracks, cols[k], sizeof(float) * (size_t)n);
+        std::memcpy(sl.h.trk[k] + sl.n_tracks, cols[k], sizeof(float) * (size_t)n);
     Request r;
     r.tag = tag;
     r.t_arrival = t_arr;
@@ -568,14 +378,13 @@ int pv_server_submit(pv_server *s, const pv_request *req, uint64_t tag, int64_t 
         sl.t_oldest = t_arr;
     sl.n_tracks += n;
     sl.n_events += 1;
-    sl.h_offsets[sl.n_events] = sl.n_tracks;
+    sl.h.offsets[sl.n_events] = sl.n_tracks;
     ++s->submitted;
     if (sl.n_events >= s->cfg.max_events_per_batch)
         seal_open(*s);
     s->cv_work.notify_one();
     return PV_OK;
 }
-
 int pv_server_poll(pv_server *s, pv_completion *out, int32_t max_out, int32_t timeout_us)
 {
     if (!s || (!out && max_out > 0) || max_out < 0)
@@ -681,13 +490,8 @@ int pv_server_destroy(pv_server *s)
     }
     if (s->worker.joinable())
         s->worker.join();
-    for (auto st : s->streams)
-        (void)hipStreamSynchronize(st);
-    for (auto &sl : s->slots)
-        free_slot(sl);
-    for (auto st : s->streams)
-        (void)hipStreamDestroy(st);
-    delete s;
+    s->dev->synchronize();
+    delete s;   // the device side frees its buffers
     return PV_OK;
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpvfind.so")
 
 PV_OK, PV_EINVAL, PV_EHIP, PV_ENOMEM, PV_EBUSY = 0, -1, -2, -3, -4
 PV_EV_NONFINITE_INPUT, PV_EV_TOO_MANY_TRACKS, PV_EV_VERTEX_OVERFLOW, PV_EV_OFFSETS_INVALID = 1, 2, 4, 8
+PV_EV_FIT_FAILED = 16
 PV_VX_NOT_CONVERGED, PV_VX_FP64_INVERSION = 1, 2
 
 

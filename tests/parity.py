@@ -1,7 +1,8 @@
 """Element-by-element comparison of the HIP path with the CPU oracle.
 
 Bars (the same inputs on both sides):
-* bit-exact: per-event status, histogram, per-track z_poca / sigma_poca /
+* bit-exact: per-event status (without the failed-fit bit when fits are not
+  compared), histogram, per-track z_poca / sigma_poca /
   central bin (the binary32 stage), cluster bounds and peaks, association
   (kept flags, owned bins, track counts), vertex counts, per-track vertex ids;
 * positions within POS_TOL_MM = 1e-3 mm and Tukey weights within
@@ -103,8 +104,11 @@ def compare(batch, g: "pv.HostResult", o: "oracle.OracleResult", debug: bool = F
     """Compare everything; with fit=False only the stages defined bit-exactly
     (status, binary32 projection, histogram, clusters, association)."""
     r = Report(n_events=batch.n_events, n_tracks=batch.n_tracks)
-    if not np.array_equal(g.status, o.status):
-        bad = np.nonzero(g.status != o.status)[0][:5]
+    # a failed fit is a fit result: without the fit comparison its flag is not compared either
+    smask = ~0 if fit else ~oracle.EV_FIT_FAILED
+    gs, os_ = g.status & smask, o.status & smask
+    if not np.array_equal(gs, os_):
+        bad = np.nonzero(gs != os_)[0][:5]
         r.fail(f"status differs at events {bad.tolist()}: gpu {g.status[bad].tolist()} oracle {o.status[bad].tolist()}")
     valid_ev = (o.status & oracle.EV_OFFSETS_INVALID) == 0
     if debug:

@@ -120,7 +120,32 @@ def test_adversarial_events():
     two = np.concatenate([_exact_event((0.0, 0.0, 30.0), 20, rng), _exact_event((0.0, 0.0, 31.0), 20, rng)])
     evs.append(two)                                                         # two vertices 1 mm apart
     b = synth.from_tracks(evs)
-    check(b, name="adversarial")
+    g, o, _ = check(b, name="adversarial")
+    assert g.status[3] == pv.PV_EV_FIT_FAILED and g.n_vertices[3] == 0   # the identical-slopes event
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["partition", "multivertex"])
+def test_failed_fits_are_flagged(mode):
+    """Candidates whose fit fails (tracks along one line: a singular normal
+    matrix; tracks all 5 mm from the beam at one z: no Tukey weight at the
+    seed) are dropped and flag their event, as in the oracle; the good vertex
+    beside them is written."""
+    rng = np.random.default_rng(33)
+    evs = []
+    for z0 in (-300.0, -40.0, 60.0, 250.0):
+        good = _exact_event((0.0, 0.0, z0), 15, rng)
+        line = np.array([[0.25 * d, -0.125 * d, z0 + 80.0 + d, 0.25, -0.125, 2.0 ** -11, 0, 0]
+                         for d in (0.0, 2.0, -1.5, 1.0) * 3])
+        off = np.array([[px + tx * d, py + ty * d, z0 - 70.0 + d, tx, ty, 2.0 ** -11, 0, 0]
+                        for k, d in enumerate((0.0, 2.0, -1.5) * 4)
+                        for (px, py, tx, ty) in [((5.0, 0.0, 0.0, 0.25), (0.0, 5.0, -0.125, 0.0),
+                                                  (-5.0, 0.0, 0.0, -0.375), (0.0, -5.0, 0.25, 0.0))[k % 4]]])
+        evs += [good, np.concatenate([good, line]), np.concatenate([off, good]), np.concatenate([line, good, off])]
+    b = synth.from_tracks(evs)
+    g, o, _ = check(b, {"assoc_mode": mode}, name=f"failed fits, mode {mode}")
+    flagged = (g.status & pv.PV_EV_FIT_FAILED) != 0
+    assert not np.any(flagged[0::4]) and np.all(flagged[1::4]) and np.all(flagged[2::4]) and np.all(flagged[3::4])
+    assert np.all(g.n_vertices == 1)
 
 
 def _ill_conditioned_event(zs, n, rng, slope_sd=3e-4, sxy=1e-4):

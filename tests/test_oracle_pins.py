@@ -727,6 +727,42 @@ def test_status_bits():
     assert r.status[0] & oracle.EV_NONFINITE_INPUT and r.track_vertex[3] == -1
 
 
+def test_failed_fit_is_flagged_and_its_candidate_dropped():
+    """Tracks along one line leave the vertex undetermined along it (the normal
+    matrix of Eq. 11 is s0 [[1, 0, -tx], [0, 1, -ty], [-tx, -ty, |t|^2]], of
+    determinant 0), and tracks that all pass 5 mm from the beamline at the same
+    z keep no Tukey weight at a seed on it (chi2 = 25 mm^2 / V_x far above the
+    cut): both
+    fits fail, the event carries PV_EV_FIT_FAILED and only the good vertex is
+    written.  A clean event carries no flag."""
+    rng = np.random.default_rng(31)
+    good = _exact_tracks_through((0.0, 0.0, -40.0), 12, rng)
+    line = _exact_tracks_through((0.0, 0.0, 60.0), 12, rng)
+    line[:, 3], line[:, 4] = 0.25, -0.125
+    line[:, 0] = 0.25 * np.array([(0.0, 2.0, -1.5)[k % 3] for k in range(12)])
+    line[:, 1] = -0.125 * np.array([(0.0, 2.0, -1.5)[k % 3] for k in range(12)])
+    # tangents to the circle of radius 5 mm about the beam at z = 160: each
+    # passes closest to the beam at z = 160, at 5 mm
+    off = []
+    for k in range(12):
+        s_ = (0.25, 0.125, 0.375)[k % 3]
+        px, py, tx, ty = ((5.0, 0.0, 0.0, s_), (0.0, 5.0, -s_, 0.0), (-5.0, 0.0, 0.0, -s_), (0.0, -5.0, s_, 0.0))[k % 4]
+        d = (0.0, 2.0, -1.5)[k % 3]
+        off.append([px + tx * d, py + ty * d, 160.0 + d, tx, ty, 2.0 ** -11, 0, 0])
+    off = np.array(off)
+    for extra in (line, off):
+        r = oracle.find(synth.from_tracks([good, np.concatenate([good, extra])]), debug=True)
+        assert r.status[0] == 0 and r.n_vertices[0] == 1
+        assert r.status[1] == oracle.EV_FIT_FAILED, r.status
+        assert r.n_vertices[1] == 1 and abs(r.vertices[1, 0]["z"] + 40.0) < 1e-9
+        assert np.all(r.track_vertex[r.track_vertex.size - 12:] == -1)
+        # the failing cluster was found and kept by the association: the fit dropped it
+        assert r.n_clusters[1] == 2 and np.all(r.clusters[1, :2]["kept"] == 1)
+    for mode in ({"assoc_mode": 1},):
+        r = oracle.find(synth.from_tracks([np.concatenate([good, line])]), mode)
+        assert r.status[0] == oracle.EV_FIT_FAILED and r.n_vertices[0] == 1
+
+
 def test_peak_search_boundaries_exact_prominence_and_ties():
     """A fall and a rise of exactly dip_prom count as significant (Sec. 3.3
     reading: at least dip_prom); of tied highest bins the first is the peak,
