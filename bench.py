@@ -29,7 +29,11 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_14966_amd", "csrc", f)
                   for f in ("pvfind_kernels.hip", "pvfind_device.h", "pvfind_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pv_find_hbm_traffic.json")
-LDS_FILE = os.path.join(ROOT, "profiles", "pv_find_lds_traffic.json")
+SQ_FILE = os.path.join(ROOT, "profiles", "pv_find_sq_counters.json")
+# VALU issue peak without packed FP32: 256 CUs x 4 SIMDs, each starting one
+# wave64 instruction every 4 cycles (16 lanes), at 2.4 GHz
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4.0   # G wave-instructions/s
+STAGES = ("clear", "project_fill", "peak_search", "association", "gather", "fit", "selection", "final_outputs")
 
 
 def log(msg):
@@ -397,8 +401,12 @@ def main():
     lds = {"bound": "lds", "peak": round(lds_peak_bs / 1e9, 1), "unit": "GB/s",
            "peak_source": f"pv_measure_lds_peak: {lds_wg} workgroups of 256 threads, 16-byte conflict-free reads",
            "achieved": None, "frac": None, "lds_bytes_per_launch": None}
-    if os.path.exists(LDS_FILE):
-        with open(LDS_FILE) as f:
+    # what does bound it: VALU issue, from the same profiled run's instruction count
+    valu = {"bound": "valu_issue", "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
+            "peak_source": "256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction (no packed FP32)",
+            "achieved": None, "frac": None, "insts_per_launch": None, "lane_utilisation": None}
+    if os.path.exists(SQ_FILE):
+        with open(SQ_FILE) as f:
             lf = json.load(f)
         sched_key = [schedule["waves_per_team"], schedule["track_capacity"]]
         if (lf.get("kernel_sha") == kernel_hash() and lf.get("workload") == args.workload
@@ -407,12 +415,31 @@ def main():
             lds.update(lds_bytes_per_launch=lb, achieved=round(lb / (main_us * 1e-6) / 1e9, 1),
                        frac=round(lb / (main_us * 1e-6) / lds_peak_bs, 4),
                        bank_conflict_cycle_frac=lf.get("bank_conflict_cycle_frac"))
-    log(f"LDS read peak {lds['peak']} GB/s; main kernel LDS {lds['achieved']} GB/s")
+            vi = lf.get("valu_insts_per_launch")
+            va = vi / (main_us * 1e-6) / 1e9
+            valu.update(insts_per_launch=vi, achieved=round(va, 1), frac=round(va / VALU_PEAK_GINST, 4),
+                        lane_utilisation=lf.get("valu_lane_utilisation"))
+    log(f"LDS read peak {lds['peak']} GB/s; main kernel LDS {lds['achieved']} GB/s; VALU issue {valu['frac']}")
     kname = f"pv_find_single<{schedule['waves_per_team']}, {schedule['track_capacity']}> (main fused launch)"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "algorithmic_bytes_per_launch": abytes,
-                "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2), "lds": lds}
+                "kernel_us": round(main_us, 2), "large_event_kernel_us": round(large_us, 2), "lds": lds,
+                "valu": valu}
+
+    # where an event's time goes: the kernel's own clock stamps between its
+    # steps (the debug form of the same kernel, only the stamps written;
+    # shader-clock cycles per event, mean over the batch)
+    cyc = torch.zeros(db.n_events * 8, dtype=torch.int32, device=dev)
+    dbg = pv.pv_debug_out(None, None, None, None, None, None, cyc.data_ptr())
+    rc = L.pv_find_debug(ctypes.byref(tr), offs, db.n_events, ctypes.byref(bl), ctypes.byref(params),
+                         ctypes.byref(ov), ctypes.byref(ot), ctypes.byref(dbg), None, st)
+    if rc != 0:
+        raise RuntimeError(pv.pv_last_error())
+    c = cyc.cpu().numpy().view(np.uint32).reshape(db.n_events, 8).astype(np.float64)
+    stage_cycles = {n: round(float(c[:, k].mean()), 1) for k, n in enumerate(STAGES)}
+    stage_cycles["total"] = round(float(c.sum(axis=1).mean()), 1)
+    log(f"cycles per event by step: {stage_cycles}")
 
     # the GPU variant of the association and fit (Eq. 18 weights over every
     # candidate), same batch and schedule, same timing
@@ -492,7 +519,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_events": batch.n_events, "n_tracks": batch.n_tracks,
                    "n_vertices": nv, "schedule": schedule},
-        "step_us": step_us, "roofline": roofline, "cpu_baseline": cpu, "per_event_launch": per_event,
+        "step_us": step_us, "roofline": roofline, "stage_cycles": stage_cycles, "cpu_baseline": cpu,
+        "per_event_launch": per_event,
         "multivertex": multivertex, "end_to_end_pcie": e2e, "served": served, "batched_configs": batched_configs,
     }
     print(json.dumps(line), flush=True)

@@ -275,10 +275,15 @@ int pv_find_debug(const pv_tracks *tracks, const int32_t *event_offsets, int32_t
  * overwritten (they end up holding the result of the winning schedule, which
  * equals every other schedule's in its integer outputs).
  *  reps       : timed launches per schedule, >= 1.
- *  cache_path : text file keeping one line per (device, key); NULL for none.
- *               With an entry for (device, key) and force == 0 nothing is
- *               timed: the cached schedule becomes the default.
- *  key        : caller's name for the workload shape (no tabs/newlines).
+ *  cache_path : text file keeping one line per (device, key, batch shape);
+ *               NULL for none.  The shape is read from the batch: its event
+ *               count and the median, 90th and 99th percentile and maximum
+ *               of its track counts, each in quarter-octave buckets, and the
+ *               association and splitting variants.  With an entry for
+ *               (device, key, shape) and force == 0 nothing is timed: the
+ *               cached schedule becomes the default.
+ *  key        : caller's name for the workload (no tabs/newlines); may be
+ *               NULL, the shape alone then keys the cache.
  *  best       : receives the chosen schedule; may be NULL.
  *  best_us    : receives its time per launch in microseconds (0 when read
  *               from the cache); may be NULL.

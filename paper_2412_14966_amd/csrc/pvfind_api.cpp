@@ -3,6 +3,7 @@
 // benchmark timing records (validation and parameters: pvfind_params.cpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -257,6 +258,35 @@ bool read_cache(const char *path, const std::string &dev, const std::string &key
     return found;
 }
 
+// Shape of a batch for the autotuner's cache: the event count and the
+// track-count distribution (median, 90th and 99th percentiles, maximum), each
+// in quarter-octave buckets (about 19 % wide), and the association and
+// splitting variants, which select different kernels.  Batches of one shape
+// share a cache entry; another pile-up or batch size gets its own.
+int workload_shape(const int32_t *offsets, int n_events, const pv_params *p, hipStream_t st, std::string &out)
+{
+    std::vector<int32_t> off((size_t)n_events + 1);
+    hipError_t err = hipMemcpyAsync(off.data(), offsets, sizeof(int32_t) * off.size(), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess)
+        err = hipStreamSynchronize(st);
+    if (err != hipSuccess)
+        return pvk::set_error(PV_EHIP, "autotune: reading the offsets: %s", hipGetErrorString(err));
+    std::vector<int> n((size_t)n_events);
+    for (int e = 0; e < n_events; ++e) {
+        const int a = off[(size_t)e], b = off[(size_t)e + 1];
+        n[(size_t)e] = (a >= 0 && b >= a) ? b - a : 0;
+    }
+    std::sort(n.begin(), n.end());
+    auto bucket = [](double x) { return x < 1.0 ? 0 : 1 + (int)std::floor(4.0 * std::log2(x)); };
+    auto q = [&](double f) { return n.empty() ? 0.0 : (double)n[(size_t)std::min<double>(f * n.size(), n.size() - 1)]; };
+    std::ostringstream o;
+    o << "E" << bucket((double)n_events) << ".p50_" << bucket(q(0.5)) << ".p90_" << bucket(q(0.9)) << ".p99_"
+      << bucket(q(0.99)) << ".max" << bucket(n.empty() ? 0.0 : (double)n.back()) << ".a" << p->assoc_mode << "p"
+      << p->peak_mode;
+    out = o.str();
+    return PV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,14 +298,24 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
 {
     if (reps < 1)
         return pvk::set_error(PV_EINVAL, "autotune: reps must be >= 1");
-    if (cache_path && !key)
-        return pvk::set_error(PV_EINVAL, "autotune: a cache needs a key");
     if (key && (std::strchr(key, '\t') || std::strchr(key, '\n')))
         return pvk::set_error(PV_EINVAL, "autotune: key must not contain tabs or newlines");
+    int rc = pvk::check_find_args(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights);
+    if (rc != PV_OK)
+        return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const std::string dev = device_tag();
+    std::string entry;   // the cache key: the caller's key and the batch's shape
+    if (cache_path) {
+        std::string shape;
+        rc = workload_shape(event_offsets, n_events, params, st, shape);
+        if (rc != PV_OK)
+            return rc;
+        entry = std::string(key ? key : "") + "|" + shape;
+    }
     pv_schedule chosen{};
     double chosen_us = 0.0;
-    if (cache_path && !force && read_cache(cache_path, dev, key, chosen)) {
+    if (cache_path && !force && read_cache(cache_path, dev, entry, chosen)) {
         int rc = pv_set_schedule(&chosen);
         if (rc == PV_OK) {
             if (best)
@@ -285,7 +325,6 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
         }
         return rc;
     }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess)
         return pvk::set_error(PV_EHIP, "hipEventCreate failed");
@@ -293,7 +332,6 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
         (void)hipEventDestroy(e0);
         return pvk::set_error(PV_EHIP, "hipEventCreate failed");
     }
-    int rc = PV_OK;
     bool have = false;
     const int waves[3] = {1, 2, 4}, caps[5] = {256, 512, 1024, 1536, 2048}, modes[2] = {2, 4};
     for (int w : waves)
@@ -348,7 +386,7 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
         std::ofstream f(cache_path, std::ios::app);
         if (!f)
             return pvk::set_error(PV_EINVAL, "autotune: cannot append to %s", cache_path);
-        f << dev << '\t' << key << '\t' << chosen.waves_per_team << ' ' << chosen.track_capacity << ' '
+        f << dev << '\t' << entry << '\t' << chosen.waves_per_team << ' ' << chosen.track_capacity << ' '
           << chosen.persistent << ' ' << chosen.teams_per_cu << ' ' << chosen_us << '\n';
     }
     rc = pv_set_schedule(&chosen);

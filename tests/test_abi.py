@@ -197,4 +197,9 @@ def test_server_and_autotune_reject_bad_arguments_on_the_host():
             ctypes.byref(ot))
     assert L.pv_autotune(*args, 0, None, None, 0, None, None, None) == pv.PV_EINVAL
     assert L.pv_autotune(*args, 3, b"/tmp/x", b"a\tb", 0, None, None, None) == pv.PV_EINVAL
-    assert L.pv_autotune(*args, 3, b"/tmp/x", None, 0, None, None, None) == pv.PV_EINVAL
+    # null arrays and negative counts are refused before the offsets are read for the cache key
+    tr0 = pv.pv_tracks(*([fake] * 7 + [None]))
+    args0 = (ctypes.byref(tr0),) + args[1:]
+    assert L.pv_autotune(*args0, 3, b"/tmp/x", None, 0, None, None, None) == pv.PV_EINVAL
+    argsn = args[:2] + (-1,) + args[3:]
+    assert L.pv_autotune(*argsn, 3, b"/tmp/x", b"k", 0, None, None, None) == pv.PV_EINVAL

@@ -189,6 +189,20 @@ def test_autotune_picks_a_schedule_and_keeps_results(tmp_path):
         s = pv.pv_get_schedule()
         assert (s.waves_per_team, s.track_capacity, s.persistent) == (best["waves_per_team"],
                                                                     best["track_capacity"], best["persistent"])
+        # another shape under the same key (mu = 40) is timed and cached on its own line
+        b40 = synth.generate("pp_mu40_20kev", n_events=500, keep_truth=False)
+        d40 = pv.to_device(b40)
+        o40 = pv.alloc_outputs(d40, p.max_vertices_per_event)
+        best3, us3 = pv.pv_autotune(d40, o40, p, reps=2, cache_path=cache, key="mu5_2k")
+        assert us3 > 0
+        best4, us4 = pv.pv_autotune(d40, o40, p, reps=2, cache_path=cache, key="mu5_2k")
+        assert best4 == best3 and us4 == 0.0
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 2 and lines[0].split("\t")[1] != lines[1].split("\t")[1]
+        say(f"autotune cache: {lines}")
+        s = pv.pv_get_schedule()   # the last call's (cached) choice is the default
+        assert (s.waves_per_team, s.track_capacity, s.persistent) == (best4["waves_per_team"],
+                                                                    best4["track_capacity"], best4["persistent"])
     finally:
         pv.lib().pv_set_schedule(pv.ctypes.byref(old))
 
