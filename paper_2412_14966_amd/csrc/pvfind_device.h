@@ -39,6 +39,22 @@ __device__ __forceinline__ int wave_min(int v)
     return v;
 }
 
+__device__ __forceinline__ float wave_min_f(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
 // Group sums below: every lane of a group gets the same bits (the pairs
 // added are the same, addition is commutative).  Within a row of 16 lanes the
 // partners come from DPP (quad permutes, half-row and row mirrors), across
@@ -828,6 +844,41 @@ __device__ __forceinline__ MvPre mv_precut(const float t[8], float zr, float d0,
     const float ry = fmaf(d0, ty, m.Y) - p.bty * d0;
     m.chi2 = m.WT * fmaf(rx, rx, ry * ry);
     return m;
+}
+
+// The z range outside which a track cannot pass the pre-cut at any seed on
+// the beamline.  The pre-cut's residual is affine in the seed's z, with the
+// slope difference dt to the beamline, and its length is smallest at z_poca
+// (Eq. 1), so |r(z_s)|^2 >= |dt|^2 (z_s - z_poca)^2; when the covariance is
+// positive semi-definite, V_x(z_s) of Eq. 2 is at most
+// (sigma_x + |z_s - z| sigma_tx)^2.  chi2 < cut then needs
+// |z_s - z_poca| < s (sigma_x + |z_poca - z| sigma_tx) / (|dt| - s sigma_tx),
+// s = sqrt(cut).  The bound is widened by 0.2 % and 1 micrometre, far above
+// its binary32 rounding, so a seed outside the range fails the cut by a wide
+// margin.  Tracks without a finite bound get the whole axis.
+__device__ __forceinline__ void mv_window(const float t[8], const KParams &p, float &zlo, float &zhi)
+{
+    zlo = -INFINITY;
+    zhi = INFINITY;
+    const float dtx = t[3] - p.btx, dty = t[4] - p.bty;
+    const float den = fmaf(dtx, dtx, dty * dty);
+    const float vxx = t[5], vxtx = t[6], vtxtx = t[7];
+    if (!(den > 0.0f) || !(vxx > 0.0f) || !(vtxtx >= 0.0f) || !(vxtx * vxtx <= vxx * vtxtx) || !isfinite(den) ||
+        !isfinite(vxx) || !isfinite(vtxtx))
+        return;
+    // hardware square roots and reciprocals (1 ulp): the widening covers them
+    const float zp = t[2] + fmaf(dtx, p.bx - t[0], dty * (p.by - t[1])) * __builtin_amdgcn_rcpf(den);
+    const float s = 1.001f * __builtin_amdgcn_sqrtf(p.chi2_window_mv);
+    const float stx = __builtin_amdgcn_sqrtf(vtxtx);
+    const float g = __builtin_amdgcn_sqrtf(den) - s * stx;
+    if (!(g > 0.0f) || !isfinite(zp))
+        return;
+    const float A =
+        fmaf(1.001f * s, fmaf(fabsf(zp - t[2]), stx, __builtin_amdgcn_sqrtf(vxx)) * __builtin_amdgcn_rcpf(g), 1e-3f);
+    if (!isfinite(A))
+        return;
+    zlo = zp - A;
+    zhi = zp + A;
 }
 
 // Stage boundaries for the per-stage cycle counters of the debug variant.

@@ -36,6 +36,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace pvk {
 
@@ -52,6 +53,7 @@ struct VertexFit {
 
 constexpr int kPages = 20;          // touched 64-bin histogram words a small team holds
 constexpr int kSmallVertices = 48;  // clusters a small team of up to 512 tracks holds (64 above)
+constexpr int kMvSortMin = 16;      // candidates from which the multi-vertex pre-cut takes tracks in z order
 
 // LDS of one team.  Large-event teams hold the whole histogram.  Small teams
 // hold only the touched 64-bin words ("pages"): word w lives in page
@@ -105,6 +107,7 @@ struct __align__(16) Smem {
     float czz[MV ? V : 1];   // multi-vertex: C_zz for the duplicate test
     unsigned long long occ;
     int ev, status, n_cl, n_live, done, n_keep, defer, n_slots;
+    int zord;                // multi-vertex: the candidates' seeds are in z order
 };
 
 // the histogram as the team holds it: h[j + off] is bin j
@@ -942,36 +945,167 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
         __syncthreads();
         nl = S.n_live;
         stamp<DEBUG>(ts, 4);
-        auto chunk_tracks = [&](int c0, float t[8]) __attribute__((always_inline)) {
-            if (c0 == r0) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    t[q] = gnext[q];
-            } else if (c0 + lane < r1) {
-                load_track(A, a + c0 + lane, t);
+        // With many candidates (high pile-up) each wavefront takes its tracks
+        // in z order, 64 at a time, and skips the candidates whose seed lies
+        // outside the union of the chunk's pre-cut ranges (mv_window): those
+        // pairs fail the cut by a wide margin, so the lists are the same as
+        // with every candidate tried.  The order comes from a stable counting
+        // sort on 4 mm buckets of the central bin; sorted position j holds its
+        // track index in the upper half of tb[j] (free in this variant).
+        // Lists are then ordered by candidate and, within one, by that order.
+        const bool zsort = nl >= kMvSortMin;
+        if (zsort) {
+            // the candidates' seeds (C_zz's array is free until the counting
+            // pass); the peak search emits them in z order, which lets a chunk
+            // find its candidates by two ballots (checked: out of order, each
+            // candidate is tested against the chunk's range instead)
+            if (wave == 0) {
+                bool ordered = true;
+                for (int k = lane; k < nl; k += 64) {
+                    const float zk = bin_centre(S.cpk[k], p) + S.cd0[k];
+                    S.czz[k] = zk;
+                    if (k > 0)
+                        ordered = ordered && (bin_centre(S.cpk[k - 1], p) + S.cd0[k - 1] <= zk);
+                }
+                const bool all = __ballot(!ordered) == 0ull;
+                if (lane == 0)
+                    S.zord = all ? 1 : 0;
             }
+
+            static_assert(sizeof(S.u) >= sizeof(int) * W * 256, "bucket counters must fit the track arrays");
+            int *cw = reinterpret_cast<int *>(&S.u);   // [W][256] bucket counters; dead since the peak search
+            auto key_of = [&](int i) __attribute__((always_inline)) {
+                const int bin = (S.tb[i] & 0x1FFF) - 1;
+                return bin < 0 ? 255 : min(bin >> 4, 254);
+            };
+            for (int k = tid; k < W * 256; k += NT)
+                cw[k] = 0;
+            __syncthreads();
+            for (int i = r0 + lane; i < r1; i += 64)
+                atomicAdd(&cw[wave * 256 + key_of(i)], 1);
+            __syncthreads();
+            if (wave == 0) {
+                int run = 0;
+                for (int b0 = 0; b0 < 256; b0 += 64) {
+                    const int b = b0 + lane;
+                    int c = 0;
+                    for (int w = 0; w < W; ++w)
+                        c += cw[w * 256 + b];
+                    const int incl = wave_incl_scan(c, lane);
+                    int r = run + incl - c;
+                    for (int w = 0; w < W; ++w) {
+                        const int cwb = cw[w * 256 + b];
+                        cw[w * 256 + b] = r;
+                        r += cwb;
+                    }
+                    run += __shfl(incl, 63);
+                }
+            }
+            __syncthreads();
+            for (int c0 = r0; c0 < r1; c0 += 64) {
+                const int i = c0 + lane;
+                const bool valid = i < r1;
+                const int key = valid ? key_of(i) : 0;
+                // lanes with the same key: one ballot per key bit
+                unsigned long long mm = __ballot(valid);
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool set = (key >> bit) & 1;
+                    const unsigned long long bb = __ballot(set);
+                    mm &= set ? bb : ~bb;
+                }
+                const unsigned long long below = mm & lanemask_lt(lane);
+                const int pos = valid ? cw[wave * 256 + key] + __popcll(below) : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (valid && below == 0ull)
+                    cw[wave * 256 + key] += __popcll(mm);
+                __builtin_amdgcn_wave_barrier();
+                if (valid)
+                    atomicOr(&S.tb[pos], i << 16);
+            }
+            __syncthreads();
+        }
+        // the chunk of (sorted) positions c0 .. c0 + 63 of this wavefront: its
+        // tracks, their indices and, sorted (ZS), the candidates [k_lo, k_hi)
+        // whose seeds lie in the union of their pre-cut ranges.  The passes
+        // below are compiled for both orders, so that without the z order
+        // their loops stay those of the plain pre-cut.
+        auto chunk_tracks = [&](auto zs, int c0, float t[8], int &i, bool &assoc, float &zlo, float &zhi, int &k_lo,
+                                int &k_hi) __attribute__((always_inline)) {
+            constexpr bool ZS = decltype(zs)::value;
+            const int j = c0 + lane;
+            k_lo = 0;
+            k_hi = nl;
+            if constexpr (!ZS) {
+                i = (j < r1) ? j : -1;
+                if (c0 == r0) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        t[q] = gnext[q];
+                } else if (i >= 0) {
+                    load_track(A, a + i, t);
+                }
+                assoc = i >= 0 && ((S.tb[i] >> 13) & kTrAssoc);
+            } else {
+                i = (j < r1) ? (S.tb[j] >> 16) : -1;
+                if (i >= 0)
+                    load_track(A, a + i, t);
+                assoc = i >= 0 && ((S.tb[i] >> 13) & kTrAssoc);
+                float lo = INFINITY, hi = -INFINITY;
+                if (assoc)
+                    mv_window(t, p, lo, hi);
+                zlo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min_f(lo))));
+                zhi = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max_f(hi))));
+                if (S.zord) {
+                    // seeds in order: the candidates below zlo, then those up to zhi
+                    int below = 0, upto = 0;
+                    for (int k0 = 0; k0 < nl; k0 += 64) {
+                        const int k = k0 + lane;
+                        const float zk = (k < nl) ? S.czz[k] : INFINITY;
+                        below += __popcll(__ballot(zk < zlo));
+                        upto += __popcll(__ballot(zk <= zhi));
+                    }
+                    k_lo = __builtin_amdgcn_readfirstlane(below);
+                    k_hi = __builtin_amdgcn_readfirstlane(upto);
+                }
+            }
+        };
+        // seeds out of order (z order only): each candidate against the chunk's range
+        auto skip = [&](auto zs, int k, float zlo, float zhi) __attribute__((always_inline)) {
+            if constexpr (decltype(zs)::value)
+                return !S.zord && !(S.czz[k] >= zlo && S.czz[k] <= zhi);
+            else
+                return false;
         };
         // pass 1: per wavefront and candidate, the tracks passing the pre-cut,
         // and per track the sum of its terms of Eq. 18 (kept in the per-track
         // key array, unused until the final pass)
-        for (int c0 = r0; c0 < r1; c0 += 64) {
-            const int i = c0 + lane;
-            float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            chunk_tracks(c0, t);
-            const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
-            float esum = 0.0f;
-            for (int k = 0; k < nl; ++k) {
-                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
-                const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
-                if (pass)
-                    esum += __expf(-0.5f * m.chi2);
-                const unsigned long long mm = __ballot(pass);
-                if (lane == 0)
-                    S.wrun[wave][k] += __popcll(mm);
+        auto pass1 = [&](auto zs) __attribute__((always_inline)) {
+            for (int c0 = r0; c0 < r1; c0 += 64) {
+                float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                int i, k_lo, k_hi;
+                bool assoc;
+                float zlo = -INFINITY, zhi = INFINITY;
+                chunk_tracks(zs, c0, t, i, assoc, zlo, zhi, k_lo, k_hi);
+                float esum = 0.0f;
+                for (int k = k_lo; k < k_hi; ++k) {
+                    if (skip(zs, k, zlo, zhi))
+                        continue;
+                    const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
+                    const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
+                    if (pass)
+                        esum += __expf(-0.5f * m.chi2);
+                    const unsigned long long mm = __ballot(pass);
+                    if (lane == 0)
+                        S.wrun[wave][k] += __popcll(mm);
+                }
+                if (i >= 0)
+                    S.u.f.BEST[i] = __float_as_uint(esum);
             }
-            if (i < r1)
-                S.u.f.BEST[i] = __float_as_uint(esum);
-        }
+        };
+        if (zsort)
+            pass1(std::true_type{});
+        else
+            pass1(std::false_type{});
         __syncthreads();
         // list lengths, starts and each wavefront's first slot per candidate
         if (wave == 0) {
@@ -1038,36 +1172,45 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
         }
         // pass 2: write the slots; the other candidates' terms of Eq. 18 are
         // the track's sum over its pre-cut passes minus this candidate's
-        for (int c0 = r0; c0 < r1; c0 += 64) {
-            const int i = c0 + lane;
-            float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            chunk_tracks(c0, t);
-            const bool assoc = i < r1 && ((S.tb[i] >> 13) & kTrAssoc);
-            float esum = 0.0f;
-            if (i < r1) {
-                esum = __uint_as_float(S.u.f.BEST[i]);
-                S.u.f.BEST[i] = 0u;
-            }
-            for (int k = 0; k < nl; ++k) {
-                const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
-                const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
-                const unsigned long long mm = __ballot(pass);
-                if (pass) {
-                    const int slot = S.wrun[wave][k] + __popcll(mm & lanemask_lt(lane));
-                    S.u.f.X[slot] = m.X;
-                    S.u.f.Y[slot] = m.Y;
-                    S.u.f.TX[slot] = t[3];
-                    S.u.f.TY[slot] = t[4];
-                    S.u.f.WT[slot] = m.WT;
-                    S.u.f.OTH[slot] = fmaxf(esum - __expf(-0.5f * m.chi2), 0.0f);
-                    S.u.f.IDX[slot] = (short)i;
+        auto pass2 = [&](auto zs) __attribute__((always_inline)) {
+            for (int c0 = r0; c0 < r1; c0 += 64) {
+                float t[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                int i, k_lo, k_hi;
+                bool assoc;
+                float zlo = -INFINITY, zhi = INFINITY;
+                chunk_tracks(zs, c0, t, i, assoc, zlo, zhi, k_lo, k_hi);
+                float esum = 0.0f;
+                if (i >= 0) {
+                    esum = __uint_as_float(S.u.f.BEST[i]);
+                    S.u.f.BEST[i] = 0u;
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0)
-                    S.wrun[wave][k] += __popcll(mm);
-                __builtin_amdgcn_wave_barrier();
+                for (int k = k_lo; k < k_hi; ++k) {
+                    if (skip(zs, k, zlo, zhi))
+                        continue;
+                    const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
+                    const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
+                    const unsigned long long mm = __ballot(pass);
+                    if (pass) {
+                        const int slot = S.wrun[wave][k] + __popcll(mm & lanemask_lt(lane));
+                        S.u.f.X[slot] = m.X;
+                        S.u.f.Y[slot] = m.Y;
+                        S.u.f.TX[slot] = t[3];
+                        S.u.f.TY[slot] = t[4];
+                        S.u.f.WT[slot] = m.WT;
+                        S.u.f.OTH[slot] = fmaxf(esum - __expf(-0.5f * m.chi2), 0.0f);
+                        S.u.f.IDX[slot] = (short)i;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == 0)
+                        S.wrun[wave][k] += __popcll(mm);
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
-        }
+        };
+        if (zsort)
+            pass2(std::true_type{});
+        else
+            pass2(std::false_type{});
         if (DEBUG && A.dbg_cl && wave == 0)
             for (int q = lane; q < S.n_cl; q += 64) {
                 pv_cluster c;
