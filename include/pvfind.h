@@ -343,9 +343,10 @@ int pv_measure_lds_peak(double *bytes_per_s, int32_t *workgroups, void *stream);
  * instantiated hipGraph of the pv_find launches; the graphs read the batch
  * size from device memory, so one graph serves every batch of its slot.
  * pv_server_submit copies an event into the slot that is open for
- * admission; a worker thread seals the open batch as soon as a stream is
- * free (or the oldest event has waited max_wait_us), copies it in, launches,
- * copies the results out and scatters them into the caller's host buffers.
+ * admission; a worker thread seals the open batch when it is full, or when
+ * a stream is free and either the device is idle or the oldest event has
+ * waited max_wait_us; it copies the batch in, launches, copies the results
+ * out and scatters them into the caller's host buffers.
  * Events that arrive while others are on the GPU join the next batch.
  * Admission is bounded by the slot pool (sized against the device-memory
  * budget): when every slot is busy, submit returns PV_EBUSY.
@@ -361,8 +362,10 @@ typedef struct {
     int32_t n_slots;                /* batch slots (staging + device buffers), >= 2   */
     int32_t n_streams;              /* HIP streams, >= 1; batches in flight <= this   */
     int64_t device_budget_bytes;    /* the slots' device memory must fit in this      */
-    int32_t max_wait_us;            /* seal a waiting batch after this long even when
-                                       every stream is busy                            */
+    int32_t max_wait_us;            /* with a stream free while other batches run,
+                                       seal the open batch once its oldest event has
+                                       waited this long (at once when the device is
+                                       idle); while every stream is busy it grows     */
     int32_t use_graphs;             /* 1: launch batches as hipGraphs; 0: launches    */
 } pv_server_config;
 

@@ -5,6 +5,7 @@
 // errors, shutdown) run against the CPU stand-in of fake_server_device.cpp.
 // Built with sanitizers by tests/test_host_logic.py; prints "all ok".
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -363,6 +364,47 @@ void test_back_pressure()
     std::puts("ok back-pressure");
 }
 
+// sealing: at once on an idle device; with a stream free while another batch
+// runs, after max_wait_us; while every stream is busy the batch grows
+void test_sealing_rules()
+{
+    const pv_params p = small_params();
+    auto evs = make_events(12, 50, p.max_vertices_per_event, 12);
+    pv_server_config c = small_config();
+    c.n_streams = 1;
+    c.max_wait_us = 100;
+    pv_server *s = nullptr;
+    CHECK(pv_server_create(&s, &p, &kBeam, &c, nullptr) == PV_OK);
+    fake::knobs().latency_us = 30000;
+    int d0 = fake::knobs().dispatches;
+    CHECK(pv_server_submit(s, &evs[0].req, 0, 0) == PV_OK);
+    std::this_thread::sleep_for(std::chrono::milliseconds(2));
+    CHECK(fake::knobs().dispatches == d0 + 1);   // idle device: sealed and dispatched at once
+    for (int k = 1; k <= 10; ++k) {
+        CHECK(pv_server_submit(s, &evs[(size_t)k].req, (uint64_t)k, 0) == PV_OK);
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    CHECK(fake::knobs().dispatches == d0 + 1);   // the only stream is busy: the batch grows
+    CHECK(pv_server_drain(s, 20000) == PV_OK);
+    pv_server_stats st;
+    CHECK(pv_server_get_stats(s, &st) == PV_OK && st.batches == 2 && st.mean_batch_events == 5.5);
+    CHECK(pv_server_destroy(s) == PV_OK);
+
+    c.n_streams = 2;
+    c.max_wait_us = 1000;
+    CHECK(pv_server_create(&s, &p, &kBeam, &c, nullptr) == PV_OK);
+    d0 = fake::knobs().dispatches;
+    CHECK(pv_server_submit(s, &evs[0].req, 0, 0) == PV_OK);
+    std::this_thread::sleep_for(std::chrono::milliseconds(2));
+    CHECK(pv_server_submit(s, &evs[1].req, 1, 0) == PV_OK);
+    std::this_thread::sleep_for(std::chrono::milliseconds(8));
+    CHECK(fake::knobs().dispatches == d0 + 2);   // a stream free, the first batch running: sealed after the wait
+    CHECK(pv_server_drain(s, 20000) == PV_OK);
+    CHECK(pv_server_destroy(s) == PV_OK);
+    fake::knobs().latency_us = 30;
+    std::puts("ok sealing rules");
+}
+
 void test_replay_and_concurrency()
 {
     const pv_params p = small_params();
@@ -478,6 +520,7 @@ int main()
     test_batches_and_second_copy();
     test_batch_limits();
     test_back_pressure();
+    test_sealing_rules();
     test_replay_and_concurrency();
     test_device_error_and_shutdown();
     std::puts("all ok");
