@@ -264,6 +264,20 @@ def batched_leg(pv, synth, workload: str, steps: int, warmup: int) -> dict:
     res = {"events": batch.n_events, "tracks": batch.n_tracks, "events_per_s": round(batch.n_events / (ms / 1e3), 1),
            "ms_per_step": round(ms, 5), "n_vertices": int(out.n_vertices.sum().item()), "schedule": best}
     log(f"{workload}: {res['events_per_s']:.4g} events/s under {best}")
+    # the multi-vertex variant (Eq. 18) on the same batch and schedule
+    mvp = pv.make_params({"assoc_mode": 1})
+    for _ in range(warmup):
+        pv.pv_find_sched(db, out, mvp, sched)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        pv.pv_find_sched(db, out, mvp, sched)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    res["multivertex"] = {"events_per_s": round(batch.n_events / (ms / 1e3), 1), "ms_per_step": round(ms, 5),
+                          "n_vertices": int(out.n_vertices.sum().item())}
+    log(f"{workload} multi-vertex: {res['multivertex']['events_per_s']:.4g} events/s")
     del db, out
     return res
 
