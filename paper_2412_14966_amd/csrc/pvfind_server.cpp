@@ -177,7 +177,7 @@ void worker_main(pv_server *sp)
     pv_server &s = *sp;
     s.dev->bind_thread();
     std::vector<pv_completion> done;
-    std::vector<int> finished;
+    std::vector<int> finished, failed;
     // s.inflight is only touched by this thread; the lock guards the slot
     // states, the open / sealed queues and the completion list, which the
     // callers share.  No device call is made with the lock held.
@@ -187,7 +187,8 @@ void worker_main(pv_server *sp)
         if (!s.inflight.empty()) {
             lk.unlock();
             finished.clear();
-            int qrc = PV_OK;
+            failed.clear();
+            int crc = PV_OK;
             for (size_t i = 0; i < s.inflight.size();) {
                 const int id = s.inflight[i];
                 const int q = s.dev->query(id);
@@ -195,13 +196,18 @@ void worker_main(pv_server *sp)
                     ++i;
                     continue;
                 }
-                if (q != PV_OK && qrc == PV_OK)
-                    qrc = q;
                 s.inflight.erase(s.inflight.begin() + (long)i);
-                finished.push_back(id);
+                if (q == PV_OK) {
+                    finished.push_back(id);
+                } else {
+                    // the batch failed on the device: its results are not
+                    // delivered, and every later call reports the error
+                    failed.push_back(id);
+                    if (crc == PV_OK)
+                        crc = q;
+                }
             }
             done.clear();
-            int crc = qrc;
             for (int id : finished) {
                 const int rc = complete(s.slots[id], done);
                 if (rc != PV_OK && crc == PV_OK)
@@ -215,7 +221,9 @@ void worker_main(pv_server *sp)
             s.n_completed += (int64_t)done.size();
             for (int id : finished)
                 release(s.slots[id]);
-            if (!finished.empty())
+            for (int id : failed)
+                release(s.slots[id]);
+            if (!finished.empty() || !failed.empty())
                 s.cv_done.notify_all();
         }
         // continuous batching: a batch is sealed when it is full, or when a

@@ -144,6 +144,10 @@ public:
             return PV_OK;
         if (now_ns() < s.done_at)
             return 1;
+        if (s.pending == 1 && fake::knobs().batches_done++ == fake::knobs().fail_batch_at.load()) {
+            s.pending = 0;
+            return pvk::set_error(PV_EHIP, "fake device: batch of slot %d failed", slot);
+        }
         if (s.pending == 1) {
             if (snapshot(s) != s.in_copy)
                 ++fake::knobs().staging_violations;

@@ -15,6 +15,8 @@ struct Knobs {
     std::atomic<int> latency_us{30};        // how long a dispatched batch runs
     std::atomic<int> fail_create{0};        // make_server_device returns PV_ENOMEM
     std::atomic<int> fail_dispatch_at{-1};  // the n-th dispatch (from 0) fails
+    std::atomic<int> fail_batch_at{-1};     // the n-th batch to finish (from 0) reports a device error
+    std::atomic<int> batches_done{0};
     std::atomic<int> dispatches{0};
     std::atomic<int> fetches{0};            // second copies of vertex records
     std::atomic<int> staging_violations{0}; // staging changed while its batch ran

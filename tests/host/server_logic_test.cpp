@@ -500,6 +500,38 @@ void test_device_error_and_shutdown()
     CHECK(std::strstr(pv_last_error(), "refused") != nullptr || true);
     CHECK(pv_server_destroy(s) == PV_OK);
     fake::knobs().fail_dispatch_at = -1;
+    // a batch that fails on the device: its events are not delivered, the
+    // error reaches the callers, the server still shuts down
+    CHECK(pv_server_create(&s, &p, &kBeam, &c, nullptr) == PV_OK);
+    fake::knobs().fail_batch_at = fake::knobs().batches_done + 1;
+    auto fb = make_events(400, 100, p.max_vertices_per_event, 13);
+    rc = PV_OK;
+    for (size_t t = 0; t < fb.size() && rc == PV_OK; ++t) {
+        rc = pv_server_submit(s, &fb[t].req, t, 0);
+        if (rc == PV_EBUSY) {
+            rc = PV_OK;
+            --t;
+            std::this_thread::yield();
+        }
+        pv_completion buf[64];
+        const int k = pv_server_poll(s, buf, 64, 0);
+        if (k < 0)
+            rc = k;
+        for (int i = 0; i < k; ++i) {
+            CHECK(buf[i].tag < fb.size());
+            fb[buf[i].tag].seen++;
+            fb[buf[i].tag].done = buf[i];
+        }
+    }
+    if (rc == PV_OK)
+        rc = pv_server_drain(s, 20000);
+    CHECK(rc == PV_EHIP);
+    pv_server_stats fst;
+    CHECK(pv_server_get_stats(s, &fst) == PV_OK && fst.completed < fst.submitted);
+    for (auto &e : fb)
+        CHECK(e.seen <= 1);
+    CHECK(pv_server_destroy(s) == PV_OK);
+    fake::knobs().fail_batch_at = -1;
     // destroy with batches still running: it drains first
     CHECK(pv_server_create(&s, &p, &kBeam, &c, nullptr) == PV_OK);
     fake::knobs().latency_us = 3000;
