@@ -175,6 +175,113 @@ def end_to_end_leg(pv, batch, params, steps):
     return res
 
 
+def end_to_end_streams_leg(pv, batch, params, steps, chunks=2, n_streams=2):
+    """The same transfers with the batch cut into `chunks` contiguous event
+    ranges issued round robin on `n_streams` streams (the paper overlaps
+    transfers and kernels on several streams, Sec. 6): per range, its tracks
+    and offsets go in, pv_find and the compaction run on the range, and its
+    counts, statuses, record offsets, records and per-track outputs come
+    back, so one range's copies overlap another's kernels and copies in the
+    other direction.  The records' copy is sized before their number is
+    known (2 per event plus 1 per 16 tracks of the range); a range with more
+    gets a second copy after the step (counted).  Two ranges on two streams
+    measured best: with more, the per-copy overheads of the 8 column copies
+    per range outweigh the overlap."""
+    import torch
+    L = pv.lib()
+    ne, nt, mv = batch.n_events, batch.n_tracks, params.max_vertices_per_event
+    offs = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    host_cols = [torch.from_numpy(np.ascontiguousarray(c)).pin_memory() for c in batch.fields()]
+    host_offs = torch.from_numpy(np.ascontiguousarray(batch.offsets, dtype=np.int32)).pin_memory()
+    db = pv.to_device(batch)
+    out = pv.alloc_outputs(db, mv)
+    dev = out.vertices.device
+    dense = torch.empty(ne * mv * 64, dtype=torch.uint8, device=dev)      # range c's records from 64 * mv * e0
+    first = torch.empty(ne + chunks, dtype=torch.int32, device=dev)       # range c's offsets from e0 + c
+    h_nv = torch.empty(ne, dtype=torch.int32).pin_memory()
+    h_st = torch.empty(ne, dtype=torch.int32).pin_memory()
+    h_first = torch.empty(ne + chunks, dtype=torch.int32).pin_memory()
+    h_tv = torch.empty(nt, dtype=torch.int32).pin_memory()
+    h_tw = torch.empty(nt, dtype=torch.float32).pin_memory()
+    h_v = torch.empty(ne * mv * 64, dtype=torch.uint8).pin_memory()
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    bounds = [int(round(ne * c / chunks)) for c in range(chunks + 1)]
+    tr, bl, _, _ = pv._args(db, out, params)
+    ot = pv.pv_track_out(out.track_vertex.data_ptr(), out.track_weight.data_ptr())
+    stats = {"second_copies": 0, "d2h": 0}
+
+    def step():
+        budget = []
+        for c in range(chunks):
+            e0, e1 = bounds[c], bounds[c + 1]
+            t0, t1 = int(offs[e0]), int(offs[e1])
+            n = e1 - e0
+            s = streams[c % n_streams]
+            st = ctypes.c_void_p(s.cuda_stream)
+            with torch.cuda.stream(s):
+                for d, h in zip(db.cols, host_cols):
+                    d[t0:t1].copy_(h[t0:t1], non_blocking=True)
+                db.offsets[e0:e1 + 1].copy_(host_offs[e0:e1 + 1], non_blocking=True)
+            vo = out.vertices.data_ptr() + 64 * mv * e0
+            ov = pv.pv_vertices_out(vo, out.n_vertices.data_ptr() + 4 * e0, out.status.data_ptr() + 4 * e0)
+            rc = L.pv_find(ctypes.byref(tr), ctypes.c_void_p(db.offsets.data_ptr() + 4 * e0), n, ctypes.byref(bl),
+                           ctypes.byref(params), ctypes.byref(ov), ctypes.byref(ot), st)
+            if rc == 0:
+                rc = L.pv_compact_vertices(ctypes.c_void_p(vo), ctypes.c_void_p(out.n_vertices.data_ptr() + 4 * e0), n,
+                                           mv, ctypes.c_void_p(dense.data_ptr() + 64 * mv * e0),
+                                           ctypes.c_void_p(first.data_ptr() + 4 * (e0 + c)), st)
+            if rc != 0:
+                raise RuntimeError(pv.pv_last_error())
+            nrec = min(mv * n, 2 * n + (t1 - t0) // 16)
+            budget.append(nrec)
+            with torch.cuda.stream(s):
+                h_nv[e0:e1].copy_(out.n_vertices[e0:e1], non_blocking=True)
+                h_st[e0:e1].copy_(out.status[e0:e1], non_blocking=True)
+                h_first[e0 + c:e1 + c + 1].copy_(first[e0 + c:e1 + c + 1], non_blocking=True)
+                b0 = 64 * mv * e0
+                h_v[b0:b0 + 64 * nrec].copy_(dense[b0:b0 + 64 * nrec], non_blocking=True)
+                h_tv[t0:t1].copy_(out.track_vertex[t0:t1], non_blocking=True)
+                h_tw[t0:t1].copy_(out.track_weight[t0:t1], non_blocking=True)
+        for s in streams:
+            s.synchronize()
+        d2h = 0
+        for c in range(chunks):
+            e0, e1 = bounds[c], bounds[c + 1]
+            total = int(h_first[e1 + c])
+            d2h += 8 * (e1 - e0) + 4 * (e1 - e0 + 1) + 64 * max(total, budget[c])
+            if total > budget[c]:   # the rest of this range's records
+                b0 = 64 * mv * e0
+                h_v[b0 + 64 * budget[c]:b0 + 64 * total].copy_(dense[b0 + 64 * budget[c]:b0 + 64 * total])
+                stats["second_copies"] += 1
+        stats["d2h"] = d2h + 8 * nt
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    stats["second_copies"] = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    dt = (time.perf_counter() - t0) / steps
+    h2d = 32 * nt + 4 * (ne + chunks)
+    res = {"events_per_s": round(ne / dt, 1), "ms_per_step": round(dt * 1e3, 4), "chunks": chunks,
+           "streams": n_streams, "h2d_bytes": h2d, "d2h_bytes": stats["d2h"],
+           "pcie_gbs": round((h2d + stats["d2h"]) / dt / 1e9, 2),
+           "second_copies_per_step": stats["second_copies"] / steps}
+    log(f"end to end, {chunks} ranges on {n_streams} streams: {res['events_per_s']:.4g} events/s "
+        f"({res['ms_per_step']:.3f} ms per step, {res['pcie_gbs']} GB/s over PCIe)")
+    # the outputs equal those of one pv_find over the whole batch (device-resident)
+    ref = pv.alloc_outputs(db, mv)
+    pv.pv_find(db, ref, params)
+    torch.cuda.synchronize()
+    res["same_as_one_launch"] = bool(torch.equal(ref.track_vertex, out.track_vertex) and
+                                     torch.equal(ref.track_weight.view(torch.int32), out.track_weight.view(torch.int32))
+                                     and torch.equal(ref.n_vertices, out.n_vertices)
+                                     and torch.equal(ref.status, out.status))
+    del db, out, dense, ref
+    return res
+
+
 def served_leg(pv, synth, n_events):
     """Continuous-batching server vs the plain one-launch-per-event server on
     the served mix (mu log-uniform in [1, 40]), host buffers in and out, so
@@ -517,6 +624,8 @@ def main():
         cpu = cpu_baseline(pv, batch, params, args.cpu_seconds)
 
     e2e = end_to_end_leg(pv, batch, params, args.e2e_steps) if args.e2e_steps > 0 else None
+    if e2e is not None:
+        e2e["streams"] = end_to_end_streams_leg(pv, batch, params, args.e2e_steps)
 
     served = None
     if args.served_events > 0:
