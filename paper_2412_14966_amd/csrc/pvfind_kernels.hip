@@ -953,12 +953,12 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
         // sort on 4 mm buckets of the central bin; sorted position j holds its
         // track index in the upper half of tb[j] (free in this variant).
         // Lists are then ordered by candidate and, within one, by that order.
-        const bool zsort = nl >= kMvSortMin;
-        if (zsort) {
+        bool zsort = false;
+        if (nl >= kMvSortMin) {
             // the candidates' seeds (C_zz's array is free until the counting
-            // pass); the peak search emits them in z order, which lets a chunk
-            // find its candidates by two ballots (checked: out of order, each
-            // candidate is tested against the chunk's range instead)
+            // pass), in z order as the peak search emits them, so that a chunk
+            // finds its candidates by two ballots; were they not in order, the
+            // event would take the plain pre-cut
             if (wave == 0) {
                 bool ordered = true;
                 for (int k = lane; k < nl; k += 64) {
@@ -971,7 +971,10 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 if (lane == 0)
                     S.zord = all ? 1 : 0;
             }
-
+            __syncthreads();
+            zsort = S.zord != 0;
+        }
+        if (zsort) {
             static_assert(sizeof(S.u) >= sizeof(int) * W * 256, "bucket counters must fit the track arrays");
             int *cw = reinterpret_cast<int *>(&S.u);   // [W][256] bucket counters; dead since the peak search
             auto key_of = [&](int i) __attribute__((always_inline)) {
@@ -1055,26 +1058,17 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                     mv_window(t, p, lo, hi);
                 zlo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min_f(lo))));
                 zhi = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max_f(hi))));
-                if (S.zord) {
-                    // seeds in order: the candidates below zlo, then those up to zhi
-                    int below = 0, upto = 0;
-                    for (int k0 = 0; k0 < nl; k0 += 64) {
-                        const int k = k0 + lane;
-                        const float zk = (k < nl) ? S.czz[k] : INFINITY;
-                        below += __popcll(__ballot(zk < zlo));
-                        upto += __popcll(__ballot(zk <= zhi));
-                    }
-                    k_lo = __builtin_amdgcn_readfirstlane(below);
-                    k_hi = __builtin_amdgcn_readfirstlane(upto);
+                // seeds in order: the candidates below zlo, then those up to zhi
+                int below = 0, upto = 0;
+                for (int k0 = 0; k0 < nl; k0 += 64) {
+                    const int k = k0 + lane;
+                    const float zk = (k < nl) ? S.czz[k] : INFINITY;
+                    below += __popcll(__ballot(zk < zlo));
+                    upto += __popcll(__ballot(zk <= zhi));
                 }
+                k_lo = __builtin_amdgcn_readfirstlane(below);
+                k_hi = __builtin_amdgcn_readfirstlane(upto);
             }
-        };
-        // seeds out of order (z order only): each candidate against the chunk's range
-        auto skip = [&](auto zs, int k, float zlo, float zhi) __attribute__((always_inline)) {
-            if constexpr (decltype(zs)::value)
-                return !S.zord && !(S.czz[k] >= zlo && S.czz[k] <= zhi);
-            else
-                return false;
         };
         // pass 1: per wavefront and candidate, the tracks passing the pre-cut,
         // and per track the sum of its terms of Eq. 18 (kept in the per-track
@@ -1088,8 +1082,6 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                 chunk_tracks(zs, c0, t, i, assoc, zlo, zhi, k_lo, k_hi);
                 float esum = 0.0f;
                 for (int k = k_lo; k < k_hi; ++k) {
-                    if (skip(zs, k, zlo, zhi))
-                        continue;
                     const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
                     const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
                     if (pass)
@@ -1185,8 +1177,6 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                     S.u.f.BEST[i] = 0u;
                 }
                 for (int k = k_lo; k < k_hi; ++k) {
-                    if (skip(zs, k, zlo, zhi))
-                        continue;
                     const MvPre m = mv_precut(t, bin_centre(S.cpk[k], p), S.cd0[k], p);
                     const bool pass = assoc && m.WT > 0.0f && m.chi2 < p.chi2_window_mv;
                     const unsigned long long mm = __ballot(pass);
