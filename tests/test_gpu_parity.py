@@ -212,6 +212,21 @@ def test_events_larger_than_a_small_team_and_too_many_tracks():
     check(b, {"max_tracks_per_event": lim}, name=f"too many tracks (limit {lim})")
 
 
+def test_event_at_the_track_limit():
+    """An event of exactly 4096 tracks (the most an event may have, held by
+    one large-event team) matches the oracle; one of 4097 is flagged
+    PV_EV_TOO_MANY_TRACKS with its tracks unassigned, on both sides."""
+    big = synth.generate("pp_mu40_20kev", n_events=3, mu=150.0)
+    rows = np.stack([np.asarray(getattr(big, f), dtype=np.float64) for f in synth.TRACK_FIELDS], 1)
+    assert rows.shape[0] >= 4097
+    b = synth.concat([synth.generate("pp_mu5_100ev", n_events=3),
+                      synth.from_tracks([rows[:4096], rows[:4097]])])
+    g, o, _ = check(b, name="4096 and 4097 tracks")
+    assert (o.status[-2] & oracle.EV_TOO_MANY_TRACKS) == 0 and o.n_vertices[-2] > 50
+    assert (o.status[-1] & oracle.EV_TOO_MANY_TRACKS) != 0 and g.n_vertices[-1] == 0
+    assert np.all(g.track_vertex[-4097:] == -1)
+
+
 def _spread_event(zs, per_vertex, rng):
     return np.concatenate([_exact_event((0.0, 0.0, float(z)), per_vertex, rng) for z in zs])
 
