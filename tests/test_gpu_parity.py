@@ -227,6 +227,27 @@ def test_event_at_the_track_limit():
     assert np.all(g.track_vertex[-4097:] == -1)
 
 
+def test_largest_batch_sampled_against_the_oracle():
+    """300,000 events at mu = 5 (39 M tracks; beyond the allocation-free
+    entry point's limit) in one call: the ordering launch runs over many
+    chunks of its counting sort and the main grid over 300,000 workgroups.
+    600 sampled events, each recomputed by the oracle alone, match."""
+    b = synth.generate_parallel("pp_mu5_10kev", n_events=300000)
+    say(f"largest batch: {b.n_events} events, {b.n_tracks} tracks")
+    g = pv.run(b)
+    rng = np.random.default_rng(50)
+    sample = np.sort(rng.choice(b.n_events, 600, replace=False))
+    sub = b.select(sample)
+    tracks = np.concatenate([np.arange(b.offsets[e], b.offsets[e + 1]) for e in sample])
+    gs = pv.HostResult(n_vertices=g.n_vertices[sample], status=g.status[sample], vertices=g.vertices[sample],
+                       track_vertex=g.track_vertex[tracks], track_weight=g.track_weight[tracks])
+    o = oracle.find(sub, parity.oracle_params(pv.pv_params_default()))
+    rep = parity.compare(sub, gs, o, debug=False)
+    say(f"largest batch sample: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+    assert rep.ties <= max(2, 0.01 * rep.n_vertices)
+
+
 def _spread_event(zs, per_vertex, rng):
     return np.concatenate([_exact_event((0.0, 0.0, float(z)), per_vertex, rng) for z in zs])
 
