@@ -623,13 +623,16 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pv, batch, params, args.cpu_seconds)
 
-    e2e = end_to_end_leg(pv, batch, params, args.e2e_steps) if args.e2e_steps > 0 else None
-    if e2e is not None:
-        e2e["streams"] = end_to_end_streams_leg(pv, batch, params, args.e2e_steps)
-
+    # the served leg before the multi-stream ones: streams torch hands out stay
+    # mapped to the process's few hardware queues and would share them with
+    # the server's
     served = None
     if args.served_events > 0:
         served = served_leg(pv, synth, args.served_events)
+
+    e2e = end_to_end_leg(pv, batch, params, args.e2e_steps) if args.e2e_steps > 0 else None
+    if e2e is not None:
+        e2e["streams"] = end_to_end_streams_leg(pv, batch, params, args.e2e_steps)
 
     # last, because each autotune run changes the library's default schedule
     batched_configs = {}

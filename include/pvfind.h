@@ -191,7 +191,8 @@ typedef struct {
 
 /* How a batch is mapped onto the GPU.  Zero fields mean "library choice". */
 typedef struct {
-    int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4 */
+    int32_t waves_per_team;            /* wavefronts cooperating on one event: 1, 2, 4,
+                                          or 8 with a track_capacity of 1024 or more  */
     int32_t track_capacity;            /* tracks per event held in LDS by small teams:
                                           256, 512, 1024, 1536 or 2048; larger events go to
                                           a second launch with 4096-track teams       */

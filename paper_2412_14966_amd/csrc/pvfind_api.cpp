@@ -333,13 +333,15 @@ int pv_autotune(const pv_tracks *tracks, const int32_t *event_offsets, int32_t n
         return pvk::set_error(PV_EHIP, "hipEventCreate failed");
     }
     bool have = false;
-    const int waves[3] = {1, 2, 4}, caps[5] = {256, 512, 1024, 1536, 2048}, modes[2] = {2, 4};
+    const int waves[4] = {1, 2, 4, 8}, caps[5] = {256, 512, 1024, 1536, 2048}, modes[2] = {2, 4};
     for (int w : waves)
         for (int c : caps)
             for (int m : modes) {
                 if (rc != PV_OK)
                     break;
                 const pv_schedule s = {w, c, m, 0};
+                if (w == 8 && c < 1024)
+                    continue;   // not a schedule (pvk::validate_schedule)
                 rc = find_impl(tracks, event_offsets, n_events, beamline, params, out_vertices, out_track_weights,
                                nullptr, &s, stream);   // warm-up, also validates the arguments
                 if (rc != PV_OK)

@@ -1780,6 +1780,9 @@ static hipError_t launch_dispatch(const KArgs &A, const pv_schedule &s, hipStrea
     case 41024: return launch_pair<4, 1024, MV, DEBUG>(A, st, ev);
     case 41536: return launch_pair<4, 1536, MV, DEBUG>(A, st, ev);
     case 42048: return launch_pair<4, 2048, MV, DEBUG>(A, st, ev);
+    case 81024: return launch_pair<8, 1024, MV, DEBUG>(A, st, ev);
+    case 81536: return launch_pair<8, 1536, MV, DEBUG>(A, st, ev);
+    case 82048: return launch_pair<8, 2048, MV, DEBUG>(A, st, ev);
     default: return hipErrorInvalidValue;
     }
 }

@@ -43,11 +43,14 @@ int set_error(int code, const char *fmt, ...)
 
 int validate_schedule(const pv_schedule &s)
 {
-    if (s.waves_per_team != 1 && s.waves_per_team != 2 && s.waves_per_team != 4)
-        return pvk::set_error(PV_EINVAL, "schedule: waves_per_team must be 1, 2 or 4 (got %d)", s.waves_per_team);
+    if (s.waves_per_team != 1 && s.waves_per_team != 2 && s.waves_per_team != 4 && s.waves_per_team != 8)
+        return pvk::set_error(PV_EINVAL, "schedule: waves_per_team must be 1, 2, 4 or 8 (got %d)", s.waves_per_team);
     if (s.track_capacity != 256 && s.track_capacity != 512 && s.track_capacity != 1024 && s.track_capacity != 1536 &&
         s.track_capacity != 2048)
         return pvk::set_error(PV_EINVAL, "schedule: track_capacity must be 256, 512, 1024, 1536 or 2048 (got %d)",
+                              s.track_capacity);
+    if (s.waves_per_team == 8 && s.track_capacity < 1024)
+        return pvk::set_error(PV_EINVAL, "schedule: eight-wavefront teams hold 1024, 1536 or 2048 tracks (got %d)",
                               s.track_capacity);
     if (s.persistent < 1 || s.persistent > 4)
         return pvk::set_error(PV_EINVAL, "schedule: persistent must be 1, 2, 3 or 4 (got %d)", s.persistent);

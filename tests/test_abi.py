@@ -160,14 +160,21 @@ def test_schedule_round_trip():
 def test_every_documented_capacity_is_accepted_and_no_other():
     old = pv.pv_get_schedule()
     try:
-        for w in (1, 2, 4):
+        for w in (1, 2, 4, 8):
             for c in (256, 512, 1024, 1536, 2048):
+                if w == 8 and c < 1024:   # eight-wavefront teams hold 1024 tracks or more
+                    with pytest.raises(pv.PvError):
+                        pv.pv_set_schedule(w, c, 4, 0)
+                    continue
                 pv.pv_set_schedule(w, c, 4, 0)
                 s = pv.pv_get_schedule()
                 assert (s.waves_per_team, s.track_capacity) == (w, c)
         for c in (0, 128, 768, 1280, 3072, 4096):
             with pytest.raises(pv.PvError):
                 pv.pv_set_schedule(2, c, 4, 0)
+        for w in (-1, 0, 3, 6, 16):
+            with pytest.raises(pv.PvError):
+                pv.pv_set_schedule(w, 1024, 4, 0)
     finally:
         pv.lib().pv_set_schedule(ctypes.byref(old))
 

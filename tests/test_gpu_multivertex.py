@@ -76,13 +76,13 @@ def test_mv_schedules_and_deferrals(sched):
 
 
 @pytest.mark.parametrize("sched", [dict(waves_per_team=w, track_capacity=c, persistent=m, teams_per_cu=0)
-                                   for (w, c, m) in ((4, 1536, 4), (1, 1024, 2), (2, 2048, 4))],
+                                   for (w, c, m) in ((4, 1536, 4), (1, 1024, 2), (2, 2048, 4), (8, 1536, 4))],
                          ids=lambda s: f"w{s['waves_per_team']}c{s['track_capacity']}m{s['persistent']}")
 def test_mv_high_pileup_precut_in_z_order(sched):
     """At mu = 40 (~35 candidates) small teams take the pre-cut's tracks in z
     order and try only the candidates within reach of each chunk: the lists,
     and so every output, still match the oracle, for one, two and four
-    wavefronts per team (the high pile-up schedule among them)."""
+    wavefronts per team and eight (the high pile-up schedule among them)."""
     b = synth.generate("pp_mu40_20kev", n_events=300, keep_truth=False)
     g, o, rep = check(b, schedule=sched, debug=False, name=f"mv mu=40 z order {sched}")
     assert rep.n_vertices > 300 * 25   # ~34 vertices per event: the z-ordered path runs

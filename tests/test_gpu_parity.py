@@ -16,7 +16,8 @@ import parity
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = [dict(waves_per_team=w, track_capacity=c, persistent=m, teams_per_cu=0)
-             for w in (1, 2, 4) for c in (256, 512, 1024, 1536, 2048) for m in (2, 4)]
+             for w in (1, 2, 4, 8) for c in (256, 512, 1024, 1536, 2048) for m in (2, 4)
+             if not (w == 8 and c < 1024)]
 WAVE = [dict(waves_per_team=1, track_capacity=c, persistent=m, teams_per_cu=0) for c in (256, 512) for m in (1, 2)]
 TEAM = dict(waves_per_team=2, track_capacity=512, persistent=2, teams_per_cu=0)
 
