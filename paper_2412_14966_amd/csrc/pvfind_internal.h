@@ -11,7 +11,7 @@ namespace pvk {
 constexpr int kMaxBins = 4096;      // histogram bins held in LDS
 constexpr int kMaxVertices = 128;   // seed clusters / vertices per event
 constexpr int kMaxTracks = 4096;    // tracks per event
-constexpr int kBigWaves = 4;        // wavefronts of a large-event team
+constexpr int kBigWaves = 8;        // wavefronts of a large-event team
 constexpr int kBigCapacity = 4096;  // tracks held in LDS by a large-event team
 
 // per-track flags packed into the LDS track word

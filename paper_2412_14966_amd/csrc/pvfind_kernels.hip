@@ -31,7 +31,7 @@
 //   select    Table 2 minimum tracks and the beamline-distance cut, prefix
 //             compaction of the kept vertices, final weights per track
 // Events with more tracks than a small team holds go to a second launch with
-// four-wavefront teams holding 4096 tracks.
+// eight-wavefront teams holding 4096 tracks.
 #include "pvfind_device.h"
 
 #include <map>
@@ -1478,7 +1478,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
             A.dbg_cycles[(size_t)e * 8 + k] = (uint32_t)(ts.t[k + 1] - ts.t[k]);
 }
 
-// Large events: a persistent grid, one four-wavefront team per CU, drains the
+// Large events: a persistent grid, one eight-wavefront team per CU, drains the
 // list of events the small teams deferred.
 template <bool MV, bool DEBUG>
 __global__ __launch_bounds__(64 * kBigWaves) void pv_find_large(KArgs A)
