@@ -15,6 +15,14 @@ namespace pvk {
 constexpr int kInfoNotConv = 1 << 8;
 constexpr int kInfoFailed = 1 << 9;
 
+// the 64-bit value of lane `src` (wavefront-uniform)
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int src)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
+    return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane)
 {
     return (1ull << lane) - 1ull;
@@ -283,7 +291,7 @@ __device__ __forceinline__ int code_at(int j, float zp, float r, const KParams &
     return edge_code(p.z_min + (float)j * p.dz, zp, r, p.unit);
 }
 
-constexpr int kShortWindow = 8;   // bins per lane in the per-lane pass
+constexpr int kShortWindow = 12;  // bins per lane in the per-lane pass
 
 // per-lane pass: windows of at most kShortWindow bins, fixed trip count and
 // no branch but the atomic's.  Edge jh (the window's last, jh <= nb) carries

@@ -609,7 +609,7 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
     stamp<DEBUG>(ts, 1);
 
     // Kernel windows of up to kShortWindow bins are filled by their own lane;
-    // wider ones (about 5 % of tracks at mu = 5) by the whole wavefront, one
+    // wider ones (about 1.6 % of tracks at mu = 5) by the whole wavefront, one
     // track at a time, so no lane idles through another lane's long window.
     // `off` maps a window's bins to LDS (0 for the whole histogram).
     auto fill_chunk = [&](bool has, float zp, float rinv, Window w, int off) __attribute__((always_inline)) {
@@ -1380,29 +1380,55 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
         if (wave == 0) {
             constexpr int KPL = (Smem<W, CAP, BIG, MV>::V + 63) / 64;   // candidates per lane
             bool ok[KPL], kept[KPL];
-            int rank[KPL];
+            int nk[KPL], rank[KPL];
             float zk[KPL], cz[KPL];
+            // dm[u][w], in the lane of candidate c = lane + 64 u: bit j set when
+            // c is a duplicate of candidate j + 64 w
+            unsigned long long dm[KPL][KPL];
             int n_ok = 0;
 #pragma unroll
             for (int u = 0; u < KPL; ++u) {
                 const int k = lane + 64 * u;
                 ok[u] = k < nl && !(S.vf.info[k] & kInfoFailed);
-                kept[u] = false;
                 zk[u] = ok[u] ? bin_centre(S.cpk[S.live[k]], p) + S.vf.dz[k] : 0.0f;
                 cz[u] = ok[u] ? S.czz[k] : 0.0f;
+                nk[u] = ok[u] ? S.ntk[k] : 0;
                 rank[u] = 0;
-                if (ok[u]) {
-                    const int nk = S.ntk[k];
-                    for (int q = 0; q < nl; ++q) {
-                        if (q == k || (S.vf.info[q] & kInfoFailed))
-                            continue;
-                        const int nq = S.ntk[q];
-                        rank[u] += (nq > nk || (nq == nk && q < k)) ? 1 : 0;
-                    }
-                }
+#pragma unroll
+                for (int w = 0; w < KPL; ++w)
+                    dm[u][w] = 0ull;
                 n_ok += __popcll(__ballot(ok[u]));
             }
+            // One candidate q at a time, broadcast from its lane: the ranks
+            // (more counted tracks first, then the lower index) and the row of
+            // candidates q is a duplicate of, which q's lane keeps.
+#pragma unroll
+            for (int uq = 0; uq < KPL; ++uq) {
+                const int lim = min(64, nl - 64 * uq);
+                for (int lq = 0; lq < lim; ++lq) {
+                    if (!__builtin_amdgcn_readlane((int)ok[uq], lq))
+                        continue;
+                    const int q = 64 * uq + lq;
+                    const int nq = __builtin_amdgcn_readlane(nk[uq], lq);
+                    const float zq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zk[uq]), lq));
+                    const float cq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cz[uq]), lq));
+#pragma unroll
+                    for (int u = 0; u < KPL; ++u) {
+                        const int k = lane + 64 * u;
+                        const bool other = ok[u] && q != k;
+                        rank[u] += (other && (nq > nk[u] || (nq == nk[u] && q < k))) ? 1 : 0;
+                        const float d = zq - zk[u];
+                        const unsigned long long row = __ballot(other && d * d < p.dup_ratio * (cq + cz[u]));
+                        if (lane == lq)
+                            dm[uq][u] = row;
+                    }
+                }
+            }
             // by rank: kept unless a duplicate of one kept before it
+            unsigned long long km[KPL];
+#pragma unroll
+            for (int w = 0; w < KPL; ++w)
+                km[w] = 0ull;
             for (int r = 0; r < n_ok; ++r) {
                 int src = 0, su = 0;
 #pragma unroll
@@ -1413,25 +1439,26 @@ __device__ __forceinline__ void process_event(Smem<W, CAP, BIG, MV> &S, const KA
                         su = u;
                     }
                 }
-                float zc = 0.0f, cc = 0.0f;
-#pragma unroll
-                for (int u = 0; u < KPL; ++u)
-                    if (u == su) {
-                        zc = __shfl(zk[u], src);
-                        cc = __shfl(cz[u], src);
-                    }
                 bool dup = false;
 #pragma unroll
-                for (int u = 0; u < KPL; ++u) {
-                    const float d = zc - zk[u];
-                    dup = dup || (kept[u] && d * d < p.dup_ratio * (cc + cz[u]));
-                }
-                const bool any = __ballot(dup) != 0ull;
+                for (int w = 0; w < KPL; ++w) {
+                    unsigned long long row = 0ull;
 #pragma unroll
-                for (int u = 0; u < KPL; ++u)
-                    if (u == su && lane == src)
-                        kept[u] = !any;
+                    for (int u = 0; u < KPL; ++u)
+                        if (u == su)
+                            row = readlane_u64(dm[u][w], src);
+                    dup = dup || (row & km[w]) != 0ull;
+                }
+                if (!dup) {
+#pragma unroll
+                    for (int u = 0; u < KPL; ++u)
+                        if (u == su)
+                            km[u] |= 1ull << src;
+                }
             }
+#pragma unroll
+            for (int u = 0; u < KPL; ++u)
+                kept[u] = ((km[u] >> lane) & 1ull) != 0ull;
             int kept_n = 0;
 #pragma unroll
             for (int u = 0; u < KPL; ++u) {
