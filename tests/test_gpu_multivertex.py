@@ -106,6 +106,18 @@ def test_mv_duplicates_and_open_selection():
     check(b, {"pv_min_pp": 0, "pv_min_gas": 0, "max_rho_pp": 1e9, "dup_ratio": 0.0}, name="mv open selection")
 
 
+def test_mv_duplicates_in_large_event_teams():
+    """Events of ~100 interactions (2,300-3,100 tracks, 68-81 vertices) go to
+    the large-event teams, whose 128 candidate slots take two per lane in the
+    duplicate test; a ratio of 10^4 makes long chains of duplicates (40-48
+    vertices kept), decided in rank order."""
+    b = synth.generate("pp_mu40_20kev", n_events=6, mu=100.0, keep_truth=False)
+    g, o, rep = check(b, name="mv large events, default ratio")
+    assert int(np.max(o.n_vertices)) > 64
+    g, o, rep = check(b, {"dup_ratio": 1e4}, name="mv duplicates, large events, R=1e4")
+    assert int(np.max(o.n_vertices)) < 50
+
+
 def test_mv_tilted_offset_beamline_and_slope_covariance():
     """Kalman-like covariances with slope terms (Eq. 2 at the seed) and a
     displaced, tilted beamline."""
