@@ -199,7 +199,8 @@ typedef struct {
     int32_t persistent;                /* 2: one team per event, hardware-scheduled;
                                           4: as 2, teams launched in the order of a
                                           counting sort by decreasing track count
-                                          (one small launch first).  1 and 3 (a
+                                          (one small launch first, sorting slices of
+                                          up to 1024 events, interleaved).  1 and 3 (a
                                           persistent grid popping a device work queue,
                                           unsorted / sorted) are rejected: with events
                                           handed to the large-team launch part-way

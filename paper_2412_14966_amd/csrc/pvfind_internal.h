@@ -42,7 +42,7 @@ struct KParams {
 
 // Device workspace of one stream: work-queue counters, the list of events
 // deferred to the large-team launch and, behind it, the processing order of
-// the sorted persistent mode (each list holds `capacity` entries).  Counters
+// the sorted mode (each list holds `capacity` entries).  Counters
 // return to zero at the end of every launch (the last workgroup to finish
 // resets them).
 struct WorkQueue {

@@ -1572,56 +1572,46 @@ __global__ __launch_bounds__(64 * W, (small_waves_per_simd<W, CAP, MV>())) void 
 }
 
 // ---------------------------------------------------------------------------
-// Processing order for the sorted persistent mode: events by decreasing track
-// count (16-track buckets, the last open-ended), so that the largest events
-// start first and the launch does not end on a long one.  A counting sort by
-// one workgroup; the order within a bucket is unspecified, which the results
-// do not depend on.  Events with invalid offsets go last.
+// Processing order of the sorted mode: events by decreasing track count
+// (16-track buckets, the last open-ended), so that the largest events start
+// first and the launch does not end on a long one.  The batch is cut into
+// G = ceil(n / 1024) slices of near-equal length (the first n mod G of them
+// one event longer); workgroup s counting-sorts slice s in LDS, one event per
+// thread, and puts its event of rank r at position r G + s.  These positions
+// are a permutation of [0, n): the r-th largest events of all slices sit side
+// by side, so the order is largest first up to the spread between slices, and
+// no workgroup depends on another.  The order within a bucket is unspecified,
+// which the results do not depend on.  Events with invalid offsets go last.
 // ---------------------------------------------------------------------------
 constexpr int kOrderBuckets = 256;
+constexpr int kOrderSlice = 1024;   // most events of one slice (one per thread)
 
-constexpr int kOrderPerThread = 16;   // events per thread and pass
-
-__global__ __launch_bounds__(1024) void order_events_kernel(const int32_t *offsets, const int32_t *n_events_dev,
-                                                            int32_t n_events_host, int32_t *order)
+__global__ __launch_bounds__(kOrderSlice) void order_events_kernel(const int32_t *offsets,
+                                                                   const int32_t *n_events_dev,
+                                                                   int32_t n_events_host, int32_t *order)
 {
     __shared__ int cnt[kOrderBuckets];
     const int tid = threadIdx.x;
     const int n_events = n_events_dev ? *n_events_dev : n_events_host;
+    const int G = (n_events + kOrderSlice - 1) / kOrderSlice;
+    const int sl = blockIdx.x;
+    if (sl >= G)   // graph replays launch the grid of the capacity
+        return;
+    const int L = n_events / G, rem = n_events % G;
+    const int first = sl * L + min(sl, rem), len = L + (sl < rem ? 1 : 0);
+    // the offset loads are issued before the counters are cleared
     const int total = offsets[n_events];
-    constexpr int kChunk = 1024 * kOrderPerThread;
-    // bucket of each of this thread's events of the chunk starting at c0 (-1:
-    // none); all the offset loads are issued before any is used
-    auto buckets = [&](int c0, int bk[kOrderPerThread]) __attribute__((always_inline)) {
-        int lo[kOrderPerThread], hi[kOrderPerThread];
-#pragma unroll
-        for (int u = 0; u < kOrderPerThread; ++u) {
-            const int e = c0 + tid + 1024 * u;
-            lo[u] = (e < n_events) ? offsets[e] : 0;
-            hi[u] = (e < n_events) ? offsets[e + 1] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kOrderPerThread; ++u) {
-            const int e = c0 + tid + 1024 * u;
-            const int a = lo[u], b = hi[u];
-            bk[u] = (e >= n_events) ? -1 : ((a < 0 || b < a || b > total) ? 0 : min((b - a) >> 4, kOrderBuckets - 1));
-        }
-    };
+    int a = 0, b = 0;
+    if (tid < len) {
+        a = offsets[first + tid];
+        b = offsets[first + tid + 1];
+    }
     for (int k = tid; k < kOrderBuckets; k += blockDim.x)
         cnt[k] = 0;
     __syncthreads();
-    int first[kOrderPerThread];   // the first chunk's buckets, kept for the second pass
-    for (int c0 = 0; c0 < n_events; c0 += kChunk) {
-        int bk[kOrderPerThread];
-        buckets(c0, bk);
-#pragma unroll
-        for (int u = 0; u < kOrderPerThread; ++u) {
-            if (bk[u] >= 0)
-                atomicAdd(&cnt[bk[u]], 1);
-            if (c0 == 0)
-                first[u] = bk[u];
-        }
-    }
+    const int bk = (tid >= len) ? -1 : ((a < 0 || b < a || b > total) ? 0 : min((b - a) >> 4, kOrderBuckets - 1));
+    if (bk >= 0)
+        atomicAdd(&cnt[bk], 1);
     __syncthreads();
     // exclusive prefix over the buckets, largest first: one wavefront
     if (tid < 64) {
@@ -1636,20 +1626,8 @@ __global__ __launch_bounds__(1024) void order_events_kernel(const int32_t *offse
         }
     }
     __syncthreads();
-    for (int c0 = 0; c0 < n_events; c0 += kChunk) {
-        int bk[kOrderPerThread];
-        if (c0 == 0) {
-#pragma unroll
-            for (int u = 0; u < kOrderPerThread; ++u)
-                bk[u] = first[u];
-        } else {
-            buckets(c0, bk);
-        }
-#pragma unroll
-        for (int u = 0; u < kOrderPerThread; ++u)
-            if (bk[u] >= 0)
-                order[atomicAdd(&cnt[bk[u]], 1)] = c0 + tid + 1024 * u;
-    }
+    if (bk >= 0)
+        order[atomicAdd(&cnt[bk], 1) * G + sl] = first + tid;
 }
 
 // ---------------------------------------------------------------------------
@@ -1761,8 +1739,11 @@ static hipError_t launch_pair(const KArgs &args, hipStream_t st, LaunchEvents *e
         A.order = nullptr;   // nothing to order
     hipError_t err = hipSuccess;
     if (A.order) {
-        hipLaunchKernelGGL(order_events_kernel, dim3(1), dim3(1024), 0, st, A.offsets, A.n_events_dev, A.n_events,
-                           A.order);
+        // one workgroup per slice of at most kOrderSlice events (of the
+        // capacity when the batch size is read from device memory)
+        const int slices = (A.n_events + kOrderSlice - 1) / kOrderSlice;
+        hipLaunchKernelGGL(order_events_kernel, dim3(slices), dim3(kOrderSlice), 0, st, A.offsets, A.n_events_dev,
+                           A.n_events, A.order);
         err = hipGetLastError();
     }
     // the main-kernel timing brackets the fused launch alone
