@@ -833,7 +833,8 @@ __device__ __forceinline__ void accumulate_mv(FitSums &a, float X, float Y, floa
 // centre is zr and seed offset d0: the track's fit frame values (position at
 // zr relative to the beamline point there, 1 / V_x of Eq. 2 at the seed) and
 // its chi2 at the seed (Eq. 7, Eq. 9).  Written out in binary32 with explicit
-// fused multiply-adds: the pre-cut is an integer decision.
+// fused multiply-adds: the pre-cut is an integer decision, the same for the
+// same inputs on every run and schedule.
 struct MvPre {
     float X, Y, WT, chi2;
 };
@@ -847,7 +848,10 @@ __device__ __forceinline__ MvPre mv_precut(const float t[8], float zr, float d0,
     m.Y = fmaf(dzr, ty, y) - (p.by + p.bty * zr);
     const float dzs = dzr + d0;
     const float V = fmaf(dzs, fmaf(dzs, t[7], 2.0f * t[6]), t[5]);
-    m.WT = (V > 0.0f && isfinite(V)) ? 1.0f / V : 0.0f;
+    // hardware reciprocal (within 1 ulp): this runs for every (track,
+    // candidate) pair, twice, and a cut decision it could move lies far inside
+    // the binary64 oracle's tie band
+    m.WT = (V > 0.0f && isfinite(V)) ? __builtin_amdgcn_rcpf(V) : 0.0f;
     const float rx = fmaf(d0, tx, m.X) - p.btx * d0;
     const float ry = fmaf(d0, ty, m.Y) - p.bty * d0;
     m.chi2 = m.WT * fmaf(rx, rx, ry * ry);
