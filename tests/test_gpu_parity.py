@@ -441,9 +441,12 @@ def test_config4_high_pileup_large_teams(cap):
           name=f"mu=40 800 events, capacity {cap}")
 
 
-def test_sorted_launch_over_several_ordering_chunks():
-    """40,000 events: the ordering launch holds 16,384 events per pass, so the
-    sorted schedule's order spans three passes; every event is compared."""
-    b = synth.generate("pp_mu5_gas_50kev", n_events=40000, keep_truth=False)
+@pytest.mark.parametrize("n_events", [1025, 40007])
+def test_sorted_launch_over_several_ordering_chunks(n_events):
+    """The ordering launch sorts slices of at most 1,024 events, one workgroup
+    each, and interleaves their ranks: 1,025 events are two slices (513 and
+    512), 40,007 are forty (seven of 1,001, the rest of 1,000), so the order
+    must still be a permutation of the batch; every event is compared."""
+    b = synth.generate("pp_mu5_gas_50kev", n_events=n_events, keep_truth=False)
     check(b, schedule=dict(waves_per_team=2, track_capacity=512, persistent=4, teams_per_cu=0), debug=False,
-          name="pp + beam-gas 40k events, sorted")
+          name=f"pp + beam-gas {n_events} events, sorted")
