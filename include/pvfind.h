@@ -220,6 +220,9 @@ int32_t pv_nbins(const pv_params *p);
 
 /* The whole path over a batch of events (Sec. 3.1-3.5).
  *  tracks        : device SoA arrays of offsets[n_events] tracks (float32).
+ *                  Every pointer must be non-null, also for a batch without
+ *                  tracks (the host cannot see offsets[n_events]); a null one
+ *                  returns PV_EINVAL.  The same holds for every output array.
  *  event_offsets : device int32[n_events + 1]; event e owns tracks
  *                  [offsets[e], offsets[e+1]); offsets[n_events] is the number
  *                  of tracks in the arrays.  Events whose offsets are negative,

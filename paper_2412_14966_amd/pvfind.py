@@ -217,7 +217,10 @@ class DeviceBatch:
 
 def to_device(batch: synth.TrackBatch, device="cuda") -> DeviceBatch:
     import torch
-    cols = [torch.from_numpy(np.ascontiguousarray(c)).to(device) for c in batch.fields()]
+    # the library takes no null track array, also for a batch without tracks:
+    # such a batch gets one unread element per column
+    cols = [torch.from_numpy(np.ascontiguousarray(c if c.size else np.zeros(1, dtype=np.float32))).to(device)
+            for c in batch.fields()]
     offs = torch.from_numpy(np.ascontiguousarray(batch.offsets, dtype=np.int32)).to(device)
     return DeviceBatch(cols=cols, offsets=offs, n_events=batch.n_events, n_tracks=batch.n_tracks,
                        beamline=tuple(batch.beamline))

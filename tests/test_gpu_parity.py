@@ -125,6 +125,36 @@ def test_adversarial_events():
     assert g.status[3] == pv.PV_EV_FIT_FAILED and g.n_vertices[3] == 0   # the identical-slopes event
 
 
+@pytest.mark.parametrize("persistent", [2, 4], ids=["batch_order", "sorted"])
+def test_empty_and_tiny_events_over_several_ordering_slices(persistent):
+    """1,500 empty events (two ordering slices, no tracks at all), then 1,100
+    events alternating empty, one to three tracks and whole mu = 5 events:
+    every event must report no vertex or the oracle's, in either order."""
+    rng = np.random.default_rng(33)
+    sched = dict(waves_per_team=2, track_capacity=512, persistent=persistent, teams_per_cu=0)
+    b = synth.from_tracks([np.zeros((0, 8)) for _ in range(1500)])
+    g, o, _ = check(b, schedule=sched, name=f"1500 empty events, mode {persistent}")
+    assert not np.any(g.n_vertices) and not np.any(g.status)
+    real = synth.generate("pp_mu5_10kev", n_events=400, keep_truth=False)
+    evs = []
+    for k in range(1100):
+        if k % 3 == 0:
+            evs.append(np.zeros((0, 8)))
+        elif k % 3 == 1:
+            t = np.zeros((int(rng.integers(1, 4)), 8))
+            t[:, 2] = rng.uniform(-50, 50, len(t))
+            t[:, 3:5] = rng.normal(0, 0.2, (len(t), 2))
+            t[:, 5] = 1e-3
+            evs.append(t)
+        else:
+            e = (k // 3) % real.n_events
+            a, z = int(real.offsets[e]), int(real.offsets[e + 1])
+            evs.append(np.stack([getattr(real, f)[a:z] for f in synth.TRACK_FIELDS], axis=1))
+    b = synth.from_tracks(evs)
+    g, o, _ = check(b, schedule=sched, name=f"1100 mixed empty/tiny/mu5 events, mode {persistent}")
+    assert np.all(g.n_vertices[0::3] == 0)
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["partition", "multivertex"])
 def test_failed_fits_are_flagged(mode):
     """Candidates whose fit fails (tracks along one line: a singular normal
