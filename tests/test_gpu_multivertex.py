@@ -118,6 +118,29 @@ def test_mv_duplicates_in_large_event_teams():
     assert int(np.max(o.n_vertices)) < 50
 
 
+def test_mv_empty_and_tiny_events():
+    """Alternating empty events, one to three tracks and mu = 5 events, over
+    two ordering slices."""
+    rng = np.random.default_rng(35)
+    real = synth.generate("pp_mu5_10kev", n_events=400, keep_truth=False)
+    evs = []
+    for k in range(1100):
+        if k % 3 == 0:
+            evs.append(np.zeros((0, 8)))
+        elif k % 3 == 1:
+            t = np.zeros((int(rng.integers(1, 4)), 8))
+            t[:, 2] = rng.uniform(-50, 50, len(t))
+            t[:, 3:5] = rng.normal(0, 0.2, (len(t), 2))
+            t[:, 5] = 1e-3
+            evs.append(t)
+        else:
+            e = (k // 3) % real.n_events
+            a, z = int(real.offsets[e]), int(real.offsets[e + 1])
+            evs.append(np.stack([getattr(real, f)[a:z] for f in synth.TRACK_FIELDS], axis=1))
+    g, o, rep = check(synth.from_tracks(evs), name="mv empty/tiny/mu5 events")
+    assert np.all(g.n_vertices[0::3] == 0)
+
+
 def test_mv_tilted_offset_beamline_and_slope_covariance():
     """Kalman-like covariances with slope terms (Eq. 2 at the seed) and a
     displaced, tilted beamline."""

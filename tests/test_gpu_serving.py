@@ -84,6 +84,52 @@ def test_served_mix_equals_batched_and_oracle(graphs, persistent):
     assert rep.ok(), "\n".join(rep.problems)
 
 
+def test_served_empty_and_tiny_events():
+    """600 empty events arriving at once (batches with no tracks at all), then
+    900 alternating empty, one to three tracks and events of the served mix:
+    the server's results equal the batched launch's and the oracle's."""
+    rng = np.random.default_rng(34)
+    mix = synth.generate("served_mulog_200kev", n_events=300, keep_truth=False)
+    evs = [np.zeros((0, 8)) for _ in range(600)]
+    for k in range(900):
+        if k % 3 == 0:
+            evs.append(np.zeros((0, 8)))
+        elif k % 3 == 1:
+            t = np.zeros((int(rng.integers(1, 4)), 8))
+            t[:, 2] = rng.uniform(-50, 50, len(t))
+            t[:, 3:5] = rng.normal(0, 0.2, (len(t), 2))
+            t[:, 5] = 1e-3
+            evs.append(t)
+        else:
+            e = k // 3
+            a, z = int(mix.offsets[e]), int(mix.offsets[e + 1])
+            evs.append(np.stack([getattr(mix, f)[a:z] for f in synth.TRACK_FIELDS], axis=1))
+    batch = synth.from_tracks(evs)
+    params = pv.make_params({"max_vertices_per_event": 96})
+    ref = pv.run(batch, pv.params_dict(params))
+    host = pv.HostEvents(batch, params.max_vertices_per_event)
+    cfg = pv.pv_server_config_default(max_events_per_batch=256, max_tracks_per_batch=256 * 600, n_slots=4,
+                                      n_streams=2, max_wait_us=100, use_graphs=1)
+    t = np.concatenate([np.zeros(600, dtype=np.int64), 1_000_000 + poisson_offsets(900, 2.0e5, seed=3)])
+    say(f"served empty/tiny: {batch.n_events} events, {batch.n_tracks} tracks")
+    with pv.Server(params, batch.beamline, cfg) as srv:
+        comp = srv.replay(host, t)
+        st = srv.stats()
+    say(f"served empty/tiny: stats {st}")
+    assert st["completed"] == batch.n_events
+    order = np.argsort(comp["tag"])
+    comp = comp[order]
+    check_same_as_batched(batch, host, ref, comp, params.max_vertices_per_event)
+    assert not np.any(comp["n_vertices"][:600]) and not np.any(comp["status"][:600])
+    o = oracle.find(batch, parity.oracle_params(params))
+    g = pv.HostResult(n_vertices=comp["n_vertices"].astype(np.int32), status=comp["status"].astype(np.int32),
+                      vertices=host.vertices[:batch.n_events], track_vertex=host.track_vertex[:batch.n_tracks],
+                      track_weight=host.track_weight[:batch.n_tracks])
+    rep = parity.compare(batch, g, o)
+    say(f"served empty/tiny vs oracle: {rep.summary()}")
+    assert rep.ok(), "\n".join(rep.problems)
+
+
 def test_served_mix_20k_events_against_the_oracle():
     """20,000 events of the served mix (mu log-uniform in [1, 40]) through the
     continuous-batching server at a Poisson rate near its capacity, in the
