@@ -125,6 +125,18 @@ def test_adversarial_events():
     assert g.status[3] == pv.PV_EV_FIT_FAILED and g.n_vertices[3] == 0   # the identical-slopes event
 
 
+@pytest.mark.parametrize("sched", [(2, 512, 4), (8, 1536, 4), (1, 256, 2)], ids=["w2c512m4", "w8c1536m4", "w1c256m2"])
+def test_single_event_batches(sched):
+    """Batches of one event (no ordering launch): a mu = 5 event, a mu = 40 one
+    and one of ~2,500 tracks, which only the large-event launch holds."""
+    s = dict(waves_per_team=sched[0], track_capacity=sched[1], persistent=sched[2], teams_per_cu=0)
+    for name, b in (("mu5", synth.generate("pp_mu5_10kev", n_events=1, first_event=6, keep_truth=False)),
+                    ("mu40", synth.generate("pp_mu40_20kev", n_events=1, first_event=3, keep_truth=False)),
+                    ("mu100", synth.generate("pp_mu40_20kev", n_events=1, mu=100.0, keep_truth=False))):
+        g, o, _ = check(b, schedule=s, name=f"one {name} event ({b.n_tracks} tracks), schedule {sched}")
+        assert g.n_vertices[0] > 0
+
+
 @pytest.mark.parametrize("persistent", [2, 4], ids=["batch_order", "sorted"])
 def test_empty_and_tiny_events_over_several_ordering_slices(persistent):
     """1,500 empty events (two ordering slices, no tracks at all), then 1,100
