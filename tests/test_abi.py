@@ -99,6 +99,8 @@ def _call(params=None, n_events=1, null=None, schedule=None):
 @pytest.mark.parametrize("null", ["track", "out", "offsets"])
 def test_null_pointers_rejected(null):
     assert _call(null=null) == pv.PV_EINVAL
+    # also for an empty batch: the host cannot see that it has no tracks
+    assert _call(null=null, n_events=0) == pv.PV_EINVAL
     assert pv.pv_last_error()
 
 
